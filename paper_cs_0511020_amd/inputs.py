@@ -1,0 +1,123 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle runs.
+
+This module only draws random lists and keys; it holds none of the sorting
+method's arithmetic.  Every generator takes a numpy ``Generator`` (PCG64) or a
+seed so that the CPU oracle and the GPU path see byte-identical inputs.
+
+A list over nodes 0..n-1 is stored structure-of-arrays: ``next[i]`` is the
+index of the node after i (NIL = 0xFFFFFFFF ends the list) and ``head`` is the
+first node.  The list order is a uniformly random permutation of the nodes, so
+node order in memory is unrelated to list order (a random single cycle cut
+open in front of a random head).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+NIL = np.uint32(0xFFFFFFFF)
+
+KEY_DTYPES = {8: np.uint8, 16: np.uint16, 32: np.uint32, 64: np.uint64}
+
+# The paper's 8-node example (Sec. 3): one-byte keys in list order 0 -> 7.
+WORKED_EXAMPLE_KEYS = np.array([21, 3, 209, 14, 156, 47, 3, 214], dtype=np.uint8)
+
+
+def rng_for(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def links_from_order(order: np.ndarray, n: int | None = None):
+    """next[] and head for the list visiting ``order`` (node ids) in sequence."""
+    order = np.asarray(order, dtype=np.uint32)
+    if n is None:
+        n = order.shape[0]
+    nxt = np.full(n, NIL, dtype=np.uint32)
+    if order.shape[0] == 0:
+        return nxt, int(NIL)
+    nxt[order[:-1]] = order[1:]
+    nxt[order[-1]] = NIL
+    return nxt, int(order[0])
+
+
+def random_list(n: int, rng: np.random.Generator):
+    """Random layout: (next, head, order) with order a uniform permutation."""
+    order = rng.permutation(n).astype(np.uint32)
+    nxt, head = links_from_order(order, n)
+    return nxt, head, order
+
+
+def identity_list(n: int):
+    """next[i] = i + 1: list order equals memory order."""
+    order = np.arange(n, dtype=np.uint32)
+    nxt, head = links_from_order(order, n)
+    return nxt, head, order
+
+
+def uniform_keys(n: int, M: int, rng: np.random.Generator) -> np.ndarray:
+    dt = KEY_DTYPES[M]
+    info = np.iinfo(dt)
+    return rng.integers(0, int(info.max), size=n, dtype=dt, endpoint=True)
+
+
+def zipf_keys(n: int, rng: np.random.Generator, s: float = 1.1,
+              distinct: int = 1 << 16) -> np.ndarray:
+    """u32 keys: ``distinct`` values drawn without repeats, rank r picked with
+    probability proportional to r^-s (truncated table, inverse CDF)."""
+    values = rng.choice(np.uint64(1) << np.uint64(32), size=distinct, replace=False)
+    values = values.astype(np.uint32)
+    ranks = np.arange(1, distinct + 1, dtype=np.float64)
+    cdf = np.cumsum(ranks ** (-s))
+    cdf /= cdf[-1]
+    u = rng.random(n)
+    r = np.searchsorted(cdf, u, side="right")
+    r = np.minimum(r, distinct - 1)
+    perm = rng.permutation(distinct)
+    return values[perm[r]]
+
+
+def few_distinct_keys(n: int, rng: np.random.Generator, count: int = 8,
+                      M: int = 32) -> np.ndarray:
+    dt = KEY_DTYPES[M]
+    info = np.iinfo(dt)
+    values = rng.choice(int(info.max) + 1 if M < 64 else (1 << 63), size=count, replace=False)
+    values = np.asarray(values).astype(dt)
+    return values[rng.integers(0, count, size=n)]
+
+
+def c2_keys(dist: str, n: int, rng: np.random.Generator) -> np.ndarray:
+    if dist == "uniform":
+        return uniform_keys(n, 32, rng)
+    if dist == "zipf":
+        return zipf_keys(n, rng)
+    if dist == "distinct8":
+        return few_distinct_keys(n, rng, 8, 32)
+    raise ValueError(dist)
+
+
+def log_uniform_lengths(count: int, lo_log2: float, hi_log2: float,
+                        rng: np.random.Generator, lo: int, hi: int) -> np.ndarray:
+    u = rng.random(count)
+    lens = np.floor(2.0 ** (lo_log2 + (hi_log2 - lo_log2) * u)).astype(np.int64)
+    return np.clip(lens, lo, hi)
+
+
+def slab_lists(lengths, rng: np.random.Generator):
+    """Many lists in contiguous node slabs; each slab gets its own random layout.
+
+    Returns (next, heads, offsets) with global node indices inside each slab.
+    """
+    lengths = np.asarray(lengths, dtype=np.int64)
+    offsets = np.zeros(lengths.shape[0] + 1, dtype=np.uint64)
+    offsets[1:] = np.cumsum(lengths)
+    total = int(offsets[-1])
+    nxt = np.full(total, NIL, dtype=np.uint32)
+    heads = np.full(lengths.shape[0], NIL, dtype=np.uint32)
+    for l, ln in enumerate(lengths):
+        if ln == 0:
+            continue
+        lo = int(offsets[l])
+        order = (rng.permutation(int(ln)) + lo).astype(np.uint32)
+        nxt[order[:-1]] = order[1:]
+        nxt[order[-1]] = NIL
+        heads[l] = order[0]
+    return nxt, heads, offsets
