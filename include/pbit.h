@@ -1,0 +1,108 @@
+/*
+ * pbit.h -- C ABI of the MI355X (gfx950) Pbit list sort.
+ *
+ * Operation (Planeta, "Pbit and other list sorting algorithms", arXiv
+ * cs/0511020, Sec. 3 and Sec. 5): a singly-linked list is re-linked so that
+ * it visits its nodes in ascending key order; nodes with equal keys keep the
+ * order they had in the input list (stable).  The key is split into M/K
+ * patterns of K bits (Sec. 4, digit (key >> s) & (2^K - 1)); the paper splits
+ * most-significant pattern first and concatenates the final groups (Sec. 5,
+ * merge of Sec. 5.1).  The GPU path produces the same permutation by ranking
+ * the list and running stable K-bit passes least-significant first; both are
+ * the unique stable sort by the full M-bit key.
+ *
+ * Data layout (structure of arrays, all DEVICE memory owned by the caller):
+ *   next[i]  index of the node after node i, or PBIT_NIL after the last node
+ *            (uint32, n entries); the node structure of Sec. 2 split into
+ *            arrays.
+ *   keys[i]  key of node i, an unsigned M-bit integer stored as uint8_t,
+ *            uint16_t, uint32_t or uint64_t for M = 8, 16, 32, 64.
+ *   head     index of the first node (Sec. 1, the root), PBIT_NIL if empty.
+ * Nodes never move: a payload attached to a node travels with its index.
+ *
+ * Flags (Sec. 6 and Sec. 7-8): PBIT_DESCENDING gives the largest key first,
+ * PBIT_SIGNED reads keys as two's-complement integers.  Equal keys keep list
+ * order in every mode.
+ *
+ * Errors are negative return values:
+ *   PBIT_EINVAL     bad argument found on the host (no device work queued):
+ *                   M not in {8,16,32,64}, K not in {0,1,2,4,8} or not
+ *                   dividing M, n >= 2^30, head >= n, null pointer,
+ *                   workspace too small (see PBIT_ENOMEM);
+ *   PBIT_EMALFORMED found on the device: an index >= n, a cycle, or a list
+ *                   whose length from head is not n; next[] is left as it
+ *                   was (the relink never runs);
+ *   PBIT_ENOMEM     workspace smaller than pbit_workspace_bytes();
+ *   PBIT_EHIP       a HIP runtime call failed.
+ */
+#ifndef PBIT_H
+#define PBIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PBIT_NIL 0xFFFFFFFFu
+#define PBIT_MAX_NODES ((1u << 30) - 1u)
+
+enum {
+    PBIT_OK = 0,
+    PBIT_EINVAL = -1,
+    PBIT_EMALFORMED = -2,
+    PBIT_ENOMEM = -3,
+    PBIT_EHIP = -4
+};
+
+enum {
+    PBIT_ASCENDING = 0,
+    PBIT_DESCENDING = 1, /* Sec. 6: largest key first                 */
+    PBIT_SIGNED = 2      /* Sec. 7-8: two's-complement keys           */
+};
+
+/*
+ * Bytes of device workspace needed to sort a list of n nodes with M-bit keys
+ * and K-bit patterns (K = 0: the library picks).  Returns 0 for arguments
+ * pbit_sort_list_async would reject.  The workspace is O(n): about
+ * n * (5 * key bytes + 17) bytes plus small per-level tables.
+ */
+size_t pbit_workspace_bytes(uint64_t n, uint32_t M, uint32_t K);
+
+/*
+ * Sort one list, asynchronously on `stream` (a hipStream_t; NULL = default
+ * stream).  Reads next_in[0..n) and keys[0..n); writes the relinked list to
+ * next_out[0..n), which may be the same array as next_in (in-place sort).
+ * d_result is device memory of two uint32 words that receive
+ * {new head, status}; status is PBIT_OK or PBIT_EMALFORMED (as uint32).  On
+ * PBIT_EMALFORMED next_out is not written.  ws is device memory of ws_bytes
+ * >= pbit_workspace_bytes(n, M, K), used only until the queued work ends.
+ * Nothing is allocated; the call may be captured in a HIP graph.  Returns
+ * PBIT_OK once the work is queued, or a host-side error (nothing queued).
+ */
+int pbit_sort_list_async(uint32_t head, const uint32_t *next_in, uint32_t *next_out,
+                         const void *keys, uint64_t n, uint32_t M, uint32_t K,
+                         uint32_t flags, uint32_t *d_result, void *ws, size_t ws_bytes,
+                         void *stream);
+
+/*
+ * Synchronous, in-place convenience form on the default stream: relinks
+ * next[] and returns the new head (PBIT_NIL for an empty list) or a negative
+ * status.  Uses a workspace the library keeps between calls (one per device,
+ * grown on demand).  next and keys are device pointers.
+ */
+int64_t pbit_sort_list(uint32_t head, uint32_t *next, const void *keys, uint64_t n,
+                       uint32_t M, uint32_t K);
+
+/* Human-readable text for a status code. */
+const char *pbit_status_string(int code);
+
+/* Library version and build information (static string). */
+const char *pbit_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PBIT_H */

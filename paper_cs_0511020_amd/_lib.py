@@ -1,0 +1,91 @@
+"""ctypes binding of libpbit.so (the C ABI in include/pbit.h).
+
+Argument marshalling only: every step of the sort runs in the HIP kernels of
+the library.  torch tensors supply device memory and the HIP stream.  There is
+no CPU fallback: if the library is missing the import of a function raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpbit.so")
+
+NIL = 0xFFFFFFFF
+MAX_NODES = (1 << 30) - 1
+OK, EINVAL, EMALFORMED, ENOMEM, EHIP = 0, -1, -2, -3, -4
+ASCENDING, DESCENDING, SIGNED = 0, 1, 2
+
+# name -> (restype, argtypes)
+_SIGNATURES = {
+    "pbit_workspace_bytes": (ctypes.c_size_t, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32]),
+    "pbit_sort_list_async": (ctypes.c_int, [
+        ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+        ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
+        ctypes.c_size_t, ctypes.c_void_p]),
+    "pbit_sort_list": (ctypes.c_int64, [
+        ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
+        ctypes.c_uint32]),
+    "pbit_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "pbit_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libpbit.so (built by ``paper_cs_0511020_amd.build``); raise if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                "libpbit.so is not built (run __graft_entry__.build() or "
+                "python -m paper_cs_0511020_amd.build); there is no fallback path")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def status_string(code: int) -> str:
+    return load().pbit_status_string(int(code)).decode()
+
+
+def version() -> str:
+    return load().pbit_version().decode()
+
+
+def workspace_bytes(n: int, M: int, K: int = 0) -> int:
+    return int(load().pbit_workspace_bytes(n, M, K))
+
+
+def _ptr(t) -> int:
+    if t is None:
+        return 0
+    return int(t.data_ptr())
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def sort_list_async(head: int, next_in, next_out, keys, n: int, M: int, K: int, flags: int,
+                    result, ws, ws_bytes: int, stream=None) -> int:
+    """Raw C-ABI call with device tensors; returns the host-side status."""
+    return int(load().pbit_sort_list_async(
+        int(head) & 0xFFFFFFFF, _ptr(next_in), _ptr(next_out), _ptr(keys), int(n), int(M),
+        int(K), int(flags), _ptr(result), _ptr(ws), int(ws_bytes), _stream_handle(stream)))
+
+
+def sort_list(head: int, next_, keys, M: int, K: int = 0) -> int:
+    """Synchronous in-place C-ABI call (library-owned workspace, default stream)."""
+    n = int(next_.numel())
+    return int(load().pbit_sort_list(int(head) & 0xFFFFFFFF, _ptr(next_), _ptr(keys), n,
+                                      int(M), int(K)))

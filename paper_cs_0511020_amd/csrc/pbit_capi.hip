@@ -1,0 +1,222 @@
+// Host side of libpbit: argument checks, the workspace plan, and the C ABI
+// declared in include/pbit.h.  All device work is queued by enqueue_sort().
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <mutex>
+
+#include "pbit.h"
+#include "pbit_internal.h"
+
+namespace pbit {
+
+hipError_t enqueue_sort(const Plan& P, uint32_t head, const uint32_t* next_in, uint32_t* next_out,
+                        const void* keys, uint32_t* d_result, char* ws, hipStream_t s);
+hipError_t enqueue_empty(uint32_t* d_result, hipStream_t s);
+size_t entry_bytes(uint32_t key_bytes);
+size_t node_bytes(uint32_t key_bytes);
+
+static size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+static uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+// Pattern width when the caller leaves it to the library.
+static uint32_t default_k(uint32_t M) { return M == 8 ? 4u : 8u; }
+
+static bool valid_shape(uint32_t M, uint32_t K)
+{
+    if (M != 8 && M != 16 && M != 32 && M != 64)
+        return false;
+    if (K != 0 && K != 1 && K != 2 && K != 4 && K != 8)
+        return false;
+    uint32_t k = K ? K : default_k(M);
+    return (M % k) == 0;
+}
+
+// Workspace layout for one list.  Returns false on arguments the C ABI rejects.
+bool make_plan(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, Plan* P)
+{
+    memset(P, 0, sizeof(*P));
+    if (!valid_shape(M, K) || (flags & ~(uint32_t)(PBIT_DESCENDING | PBIT_SIGNED)) != 0)
+        return false;
+    if (n > PBIT_MAX_NODES)
+        return false;
+    P->n = n;
+    P->M = M;
+    P->K = K ? K : default_k(M);
+    P->RB = P->K;
+    P->radix = 1u << P->K;
+    P->passes = M / P->K;
+    P->flags = flags;
+    P->key_bytes = M / 8;
+    P->items = P->key_bytes == 8 ? 8 : 16;
+    P->tile = 256 * P->items;
+    P->tiles = (uint32_t)ceil_div(n ? n : 1, P->tile);
+    if (n == 0) {
+        P->total = 256;
+        return true;
+    }
+    size_t off = 0;
+    P->o_header = off;
+    off = align_up(off + sizeof(Header));
+    P->o_hist = off;
+    off = align_up(off + (size_t)P->passes * P->radix * 4);
+    P->o_dbase = off;
+    off = align_up(off + (size_t)P->passes * P->radix * 4);
+    P->o_look = off;
+    off = align_up(off + (size_t)P->passes * P->tiles * P->radix * 4);
+    P->zero_end = off;
+    P->o_nodes = off;
+    off = align_up(off + n * node_bytes(P->key_bytes));
+    P->o_keysA = off;
+    off = align_up(off + n * P->key_bytes);
+    P->o_idxA = off;
+    off = align_up(off + n * 4);
+    P->o_keysB = off;
+    off = align_up(off + n * P->key_bytes);
+    P->o_idxB = off;
+    off = align_up(off + n * 4);
+
+    int k = 0;
+    uint64_t m = n;
+    for (;;) {
+        if (k >= kMaxLevels)
+            return false;
+        LevelPlan& L = P->lv[k];
+        L.log_l = k == 0 ? kLog0 : kLogUp;
+        L.seg_cap = k == 0 ? kSeg0 : kSegUp;
+        L.m_bound = m;
+        L.n_static = 1 + ceil_div(m, 1ull << L.log_l);
+        L.dyn_cap = ceil_div(m, L.seg_cap) + 1;
+        L.out_bound = L.n_static + L.dyn_cap;
+        L.o_rec_out = off;
+        off = align_up(off + L.out_bound * 16);
+        L.o_members = off;
+        off = align_up(off + L.out_bound * L.seg_cap *
+                                 (k == 0 ? entry_bytes(P->key_bytes) : sizeof(uint32_t)));
+        L.o_offn_out = off;
+        off = align_up(off + L.out_bound * 4);
+        k++;
+        m = L.out_bound;
+        if (m <= kBaseMax)
+            break;
+    }
+    P->levels = k;
+    P->total = off;
+    return true;
+}
+
+struct SyncCache {
+    std::mutex mu;
+    void* ws = nullptr;
+    size_t bytes = 0;
+    uint32_t* result = nullptr;
+};
+
+static SyncCache& sync_cache(int dev)
+{
+    static SyncCache caches[64];
+    return caches[dev & 63];
+}
+
+}  // namespace pbit
+
+using namespace pbit;
+
+extern "C" size_t pbit_workspace_bytes(uint64_t n, uint32_t M, uint32_t K)
+{
+    Plan P;
+    if (!make_plan(n, M, K, 0, &P))
+        return 0;
+    return P.total;
+}
+
+extern "C" int pbit_sort_list_async(uint32_t head, const uint32_t* next_in, uint32_t* next_out,
+                                    const void* keys, uint64_t n, uint32_t M, uint32_t K,
+                                    uint32_t flags, uint32_t* d_result, void* ws,
+                                    size_t ws_bytes, void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    if (!d_result || ((uintptr_t)d_result & 3u))
+        return PBIT_EINVAL;
+    Plan P;
+    if (!make_plan(n, M, K, flags, &P))
+        return PBIT_EINVAL;
+    if (n == 0) {
+        if (head != PBIT_NIL)
+            return PBIT_EINVAL;
+        return enqueue_empty(d_result, s) == hipSuccess ? PBIT_OK : PBIT_EHIP;
+    }
+    if (head >= n)
+        return PBIT_EINVAL;
+    if (!next_in || !next_out || !keys || !ws)
+        return PBIT_EINVAL;
+    if (((uintptr_t)next_in & 3u) || ((uintptr_t)next_out & 3u) ||
+        ((uintptr_t)keys & (P.key_bytes - 1)) || ((uintptr_t)ws & 255u))
+        return PBIT_EINVAL;
+    if (ws_bytes < P.total)
+        return PBIT_ENOMEM;
+    hipError_t e = enqueue_sort(P, head, next_in, next_out, keys, d_result, (char*)ws, s);
+    return e == hipSuccess ? PBIT_OK : PBIT_EHIP;
+}
+
+extern "C" int64_t pbit_sort_list(uint32_t head, uint32_t* next, const void* keys, uint64_t n,
+                                  uint32_t M, uint32_t K)
+{
+    Plan P;
+    if (!make_plan(n, M, K, 0, &P))
+        return PBIT_EINVAL;
+    if (n == 0)
+        return head == PBIT_NIL ? (int64_t)PBIT_NIL : PBIT_EINVAL;
+    if (head >= n || !next || !keys)
+        return PBIT_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return PBIT_EHIP;
+    SyncCache& c = sync_cache(dev);
+    std::lock_guard<std::mutex> lock(c.mu);
+    if (!c.result) {
+        if (hipMalloc((void**)&c.result, 256) != hipSuccess)
+            return PBIT_EHIP;
+    }
+    if (c.bytes < P.total) {
+        if (c.ws) {
+            if (hipDeviceSynchronize() != hipSuccess)
+                return PBIT_EHIP;
+            hipFree(c.ws);
+            c.ws = nullptr;
+            c.bytes = 0;
+        }
+        if (hipMalloc(&c.ws, P.total) != hipSuccess)
+            return PBIT_ENOMEM;
+        c.bytes = P.total;
+    }
+    int st = pbit_sort_list_async(head, next, next, keys, n, M, K, 0, c.result, c.ws, c.bytes,
+                                  nullptr);
+    if (st != PBIT_OK)
+        return st;
+    uint32_t res[2];
+    if (hipMemcpy(res, c.result, sizeof res, hipMemcpyDeviceToHost) != hipSuccess)
+        return PBIT_EHIP;
+    if ((int32_t)res[1] != 0)
+        return (int32_t)res[1];
+    return (int64_t)res[0];
+}
+
+extern "C" const char* pbit_status_string(int code)
+{
+    switch (code) {
+    case PBIT_OK: return "ok";
+    case PBIT_EINVAL: return "invalid argument";
+    case PBIT_EMALFORMED: return "malformed list (index out of range, cycle, or length != n)";
+    case PBIT_ENOMEM: return "workspace too small";
+    case PBIT_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+    }
+}
+
+extern "C" const char* pbit_version(void)
+{
+    return "pbit-mi355x 0.1 (gfx950)";
+}

@@ -1,0 +1,67 @@
+// Internal types shared by the host planner and the kernels of libpbit.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+namespace pbit {
+
+constexpr uint32_t kNil = 0xFFFFFFFFu;
+
+// Level 0 walks the node list; every node index that is a multiple of
+// 2^kLog0 (and the head) starts a segment, and a segment holds at most kSeg0
+// nodes (a longer stretch continues in a freshly numbered segment).
+constexpr uint32_t kLog0 = 4;
+constexpr uint32_t kSeg0 = 16;
+// Levels >= 1 walk the list of segments of the level below.
+constexpr uint32_t kLogUp = 3;
+constexpr uint32_t kSegUp = 32;
+// The last level is ranked inside one workgroup's LDS.
+constexpr uint32_t kBaseMax = 8192;
+constexpr int kMaxLevels = 12;
+constexpr int kMaxPasses = 64;
+
+// Lookback words: 2 flag bits + 30-bit count.
+constexpr uint32_t kFlagAgg = 1u << 30;
+constexpr uint32_t kFlagPrefix = 2u << 30;
+constexpr uint32_t kCountMask = (1u << 30) - 1u;
+
+struct PassSched {
+    uint32_t skip;    // every key has the same pattern: the pass is the identity
+    uint32_t in_buf;  // 0: buffer A, 1: buffer B
+    uint32_t last;    // last executed pass: writes indices only
+    uint32_t pad;
+};
+
+// Device-side header at the start of the workspace (zeroed per sort).
+struct Header {
+    int32_t status;
+    uint32_t final_buf;
+    uint32_t dyn[kMaxLevels];
+    uint32_t tile_ctr[kMaxPasses];
+    PassSched sched[kMaxPasses];
+};
+
+struct LevelPlan {
+    uint32_t log_l;       // splitter spacing 2^log_l
+    uint32_t seg_cap;     // members per chain segment
+    uint64_t m_bound;     // element ids at this level are < m_bound
+    uint64_t n_static;    // chain 0 = head chain, chain 1 + j/L for splitter j
+    uint64_t dyn_cap;     // extra chains for stretches longer than seg_cap
+    uint64_t out_bound;   // n_static + dyn_cap = element ids of the level above
+    size_t o_rec_out;     // uint4 records of the level above (out_bound)
+    size_t o_members;     // chain members (out_bound * seg_cap entries)
+    size_t o_offn_out;    // node offsets of the level-above elements (u32)
+};
+
+struct Plan {
+    uint64_t n;
+    uint32_t M, K, RB, radix, passes, flags, key_bytes;
+    uint32_t tile, tiles, items;
+    int levels;           // walk levels; the base ranks level `levels`
+    LevelPlan lv[kMaxLevels];
+    size_t o_header, o_hist, o_dbase, o_look, zero_end;
+    size_t o_nodes, o_keysA, o_idxA, o_keysB, o_idxB;
+    size_t total;
+};
+
+}  // namespace pbit

@@ -1,0 +1,884 @@
+// HIP kernels (gfx950) of the Pbit list sort.
+//
+// Path for one list of n nodes (the split/concatenate method of the paper's
+// Sec. 3 and Sec. 5, reorganised for a wide machine):
+//   pack       next[] and keys[] become one 8- or 16-byte record per node so a
+//              walk step is one random access; the histograms of every K-bit
+//              pattern are counted here (order-free).
+//   walk0      sparse-ruler list ranking, level 0: every node whose index is a
+//              multiple of 16 (and the head) starts a segment; each lane walks
+//              its segment keeping up to 16 (key, node) entries in registers,
+//              then writes them as one block.
+//   walk_up    the same on the list of segments, recursively, until the list
+//              fits one workgroup.
+//   base       pointer jumping (Wyllie) in LDS over the last level.
+//   down       offsets flow back down the levels.
+//   unchain    segment contents are copied to list order.
+//   schedule   per-pass digit bases; passes whose pattern is constant are
+//              skipped (the identity), the paper's "empty groups are omitted".
+//   digit pass stable K-bit split per pattern, least significant first:
+//              wave ballot ranking, LDS tile staging, decoupled look-back.
+//              Least-significant-first stable passes give the same order as
+//              the paper's most-significant-first recursion (both are the
+//              stable sort by the full key).
+//   relink     next[order[j]] = order[j+1], the concatenation of Sec. 5.1.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pbit.h"
+#include "pbit_internal.h"
+
+namespace pbit {
+
+// ---------------------------------------------------------------- records
+template <typename KeyT> struct NodeRec { uint32_t next; uint32_t key; };
+template <> struct __attribute__((aligned(16))) NodeRec<uint64_t> { uint32_t next; uint32_t pad; uint64_t key; };
+
+template <typename KeyT> struct Entry { uint32_t key; uint32_t idx; };
+template <> struct __attribute__((aligned(16))) Entry<uint64_t> { uint64_t key; uint32_t idx; uint32_t pad; };
+
+template <typename KeyT> __device__ __forceinline__ KeyT entry_key(const Entry<KeyT>& e) { return (KeyT)e.key; }
+
+__device__ __forceinline__ void set_error(int32_t* status, int32_t code)
+{
+    atomicCAS(status, 0, code);
+}
+
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st_agent(uint32_t* p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------- init
+__global__ void k_zero(uint32_t* __restrict__ p, size_t words)
+{
+    size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < words; i += stride)
+        p[i] = 0u;
+}
+
+// ---------------------------------------------------------------- pack
+// Node records and the count of every pattern value of every pass.
+template <typename KeyT, int RB>
+__global__ __launch_bounds__(256) void k_pack(const uint32_t* __restrict__ next,
+                                              const KeyT* __restrict__ keys, uint32_t n,
+                                              KeyT xor_mask, uint32_t passes,
+                                              NodeRec<KeyT>* __restrict__ nodes,
+                                              uint32_t* __restrict__ hist, Header* hdr)
+{
+    constexpr uint32_t RADIX = 1u << RB;
+    extern __shared__ uint32_t s_hist[];  // passes * RADIX
+    const uint32_t nbins = passes * RADIX;
+    for (uint32_t i = threadIdx.x; i < nbins; i += blockDim.x)
+        s_hist[i] = 0;
+    __syncthreads();
+    bool bad = false;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+        uint32_t nx = next[i];
+        KeyT k = keys[i] ^ xor_mask;
+        bad |= (nx != kNil) && (nx >= n);
+        NodeRec<KeyT> r;
+        r.next = nx;
+        r.key = k;
+        if constexpr (sizeof(KeyT) == 8) r.pad = 0;
+        nodes[i] = r;
+        for (uint32_t p = 0; p < passes; p++) {
+            uint32_t d = (uint32_t)(k >> (p * RB)) & (RADIX - 1u);
+            atomicAdd(&s_hist[p * RADIX + d], 1u);
+        }
+    }
+    if (bad)
+        set_error(&hdr->status, PBIT_EMALFORMED);
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nbins; i += blockDim.x) {
+        uint32_t v = s_hist[i];
+        if (v)
+            atomicAdd(&hist[i], v);
+    }
+}
+
+// ---------------------------------------------------------------- level-0 walk
+// Chain 0 starts at head, chain 1 + j/L at node j (j a multiple of L, j != head).
+// A chain runs until the next start node or NIL; every kSeg0 nodes it moves
+// on to a new segment numbered from n_static upwards.  Output per segment:
+// {successor segment, nodes, members, 0} and its (key, node) entries.
+template <typename KeyT>
+__global__ __launch_bounds__(256) void k_walk0(const NodeRec<KeyT>* __restrict__ nodes,
+                                               uint32_t n, uint32_t head, uint32_t n_static,
+                                               uint32_t dyn_cap, uint4* __restrict__ rec_out,
+                                               Entry<KeyT>* __restrict__ buf, Header* hdr)
+{
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_static)
+        return;
+    const uint32_t lmask = (1u << kLog0) - 1u;
+    uint32_t start;
+    if (c == 0) {
+        start = head;
+    } else {
+        uint64_t s = (uint64_t)(c - 1) << kLog0;
+        if (s >= n || (uint32_t)s == head) {
+            rec_out[c] = make_uint4(kNil, 0, 0, 0);
+            return;
+        }
+        start = (uint32_t)s;
+    }
+    uint32_t seg = c, cur = start;
+    for (;;) {
+        Entry<KeyT> e[kSeg0];
+        uint32_t len = 0, nx = kNil;
+        bool stop = false;
+#pragma unroll
+        for (uint32_t t = 0; t < kSeg0; t++) {
+            if (!stop) {
+                NodeRec<KeyT> r = nodes[cur];
+                e[t].key = r.key;
+                e[t].idx = cur;
+                len = t + 1;
+                nx = r.next;
+                if (nx == kNil) {
+                    stop = true;
+                } else if (nx >= n) {
+                    set_error(&hdr->status, PBIT_EMALFORMED);
+                    nx = kNil;
+                    stop = true;
+                } else if ((nx & lmask) == 0 || nx == head) {
+                    stop = true;
+                } else {
+                    cur = nx;
+                }
+            }
+        }
+        Entry<KeyT>* b = buf + (size_t)seg * kSeg0;
+#pragma unroll
+        for (uint32_t t = 0; t < kSeg0; t++)
+            if (t < len)
+                b[t] = e[t];
+        if (stop) {
+            uint32_t succ = (nx == kNil) ? kNil : (nx == head ? 0u : 1u + (nx >> kLog0));
+            rec_out[seg] = make_uint4(succ, len, len, 0);
+            return;
+        }
+        uint32_t d = atomicAdd(&hdr->dyn[0], 1u);
+        if (d >= dyn_cap) {
+            set_error(&hdr->status, PBIT_EMALFORMED);
+            rec_out[seg] = make_uint4(kNil, len, len, 0);
+            return;
+        }
+        const uint32_t nseg = n_static + d;
+        rec_out[seg] = make_uint4(nseg, len, len, 0);
+        seg = nseg;
+        cur = nx;
+    }
+}
+
+// ---------------------------------------------------------------- upper walks
+// Same ruler over the element list of level k (records {succ, nodes, ...};
+// a record with 0 nodes is an unused id).  The head of every level >= 1 is
+// element 0.  m_k = prev_static + min(prev_dyn, prev_cap).
+__global__ __launch_bounds__(256) void k_walk_up(const uint4* __restrict__ rec_in,
+                                                 uint32_t prev_static, uint32_t prev_cap,
+                                                 int prev_level, uint32_t n_static,
+                                                 uint32_t dyn_cap, int level,
+                                                 uint4* __restrict__ rec_out,
+                                                 uint32_t* __restrict__ members, Header* hdr)
+{
+    if (hdr->status != 0)
+        return;
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_static)
+        return;
+    const uint32_t m = prev_static + min(hdr->dyn[prev_level], prev_cap);
+    const uint32_t lmask = (1u << kLogUp) - 1u;
+    uint32_t start;
+    if (c == 0) {
+        start = 0;
+    } else {
+        uint64_t s = (uint64_t)(c - 1) << kLogUp;
+        if (s >= m || s == 0) {
+            rec_out[c] = make_uint4(kNil, 0, 0, 0);
+            return;
+        }
+        start = (uint32_t)s;
+    }
+    if (rec_in[start].y == 0) {  // unused id (empty chain of the level below)
+        if (c == 0)
+            set_error(&hdr->status, PBIT_EMALFORMED);
+        rec_out[c] = make_uint4(kNil, 0, 0, 0);
+        return;
+    }
+    uint32_t seg = c, cur = start;
+    for (;;) {
+        uint32_t mem[kSegUp];
+        uint32_t cnt = 0, nodes_sum = 0, nx = kNil;
+        bool stop = false;
+#pragma unroll
+        for (uint32_t t = 0; t < kSegUp; t++) {
+            if (!stop) {
+                uint4 r = rec_in[cur];
+                if (r.y == 0) {
+                    set_error(&hdr->status, PBIT_EMALFORMED);
+                    nx = kNil;
+                    stop = true;
+                } else {
+                    mem[t] = cur;
+                    cnt = t + 1;
+                    nodes_sum += r.y;
+                    nx = r.x;
+                    if (nx == kNil) {
+                        stop = true;
+                    } else if (nx >= m) {
+                        set_error(&hdr->status, PBIT_EMALFORMED);
+                        nx = kNil;
+                        stop = true;
+                    } else if ((nx & lmask) == 0) {
+                        stop = true;
+                    } else {
+                        cur = nx;
+                    }
+                }
+            }
+        }
+        uint32_t* b = members + (size_t)seg * kSegUp;
+#pragma unroll
+        for (uint32_t t = 0; t < kSegUp; t++)
+            if (t < cnt)
+                b[t] = mem[t];
+        if (stop) {
+            uint32_t succ = (nx == kNil) ? kNil : (nx == 0 ? 0u : 1u + (nx >> kLogUp));
+            rec_out[seg] = make_uint4(succ, nodes_sum, cnt, 0);
+            return;
+        }
+        uint32_t d = atomicAdd(&hdr->dyn[level], 1u);
+        if (d >= dyn_cap) {
+            set_error(&hdr->status, PBIT_EMALFORMED);
+            rec_out[seg] = make_uint4(kNil, nodes_sum, cnt, 0);
+            return;
+        }
+        const uint32_t nseg = n_static + d;
+        rec_out[seg] = make_uint4(nseg, nodes_sum, cnt, 0);
+        seg = nseg;
+        cur = nx;
+    }
+}
+
+// ---------------------------------------------------------------- base
+// Pointer jumping (Wyllie) in LDS: suffix node counts from every element to
+// the end of the list, then offset = total - suffix.  The list must end in
+// NIL from element 0 and cover exactly n nodes.
+constexpr int kBaseThreads = 1024;
+constexpr int kBasePer = kBaseMax / kBaseThreads;
+
+__global__ __launch_bounds__(kBaseThreads) void k_base(const uint4* __restrict__ rec,
+                                                       uint32_t prev_static, uint32_t prev_cap,
+                                                       int prev_level, uint32_t n_total,
+                                                       uint32_t* __restrict__ offn, Header* hdr)
+{
+    __shared__ uint32_t s_ptr[kBaseMax];
+    __shared__ uint32_t s_val[kBaseMax];
+    __shared__ int s_bad;
+    if (hdr->status != 0)
+        return;
+    const uint32_t m = min(prev_static + min(hdr->dyn[prev_level], prev_cap), kBaseMax);
+    const int tid = threadIdx.x;
+    if (tid == 0)
+        s_bad = 0;
+    for (int j = 0; j < kBasePer; j++) {
+        uint32_t i = tid + j * kBaseThreads;
+        uint32_t p = kNil, v = 0;
+        if (i < m) {
+            uint4 r = rec[i];
+            if (r.y != 0) {
+                p = r.x;
+                v = r.y;
+                if (p != kNil && p >= m)
+                    p = kNil;  // caught below: the total cannot reach n
+            }
+        }
+        s_ptr[i] = p;
+        s_val[i] = v;
+    }
+    __syncthreads();
+    int rounds = 1;
+    while ((1u << (rounds - 1)) < m)
+        rounds++;
+    for (int r = 0; r < rounds; r++) {
+        uint32_t np[kBasePer], nv[kBasePer];
+#pragma unroll
+        for (int j = 0; j < kBasePer; j++) {
+            uint32_t i = tid + j * kBaseThreads;
+            uint32_t p = s_ptr[i];
+            uint32_t v = s_val[i];
+            if (p != kNil) {
+                v += s_val[p];
+                p = s_ptr[p];
+            }
+            np[j] = p;
+            nv[j] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kBasePer; j++) {
+            uint32_t i = tid + j * kBaseThreads;
+            s_ptr[i] = np[j];
+            s_val[i] = nv[j];
+        }
+        __syncthreads();
+    }
+    const uint32_t total = s_val[0];
+    if (tid == 0 && (m == 0 || s_ptr[0] != kNil || total != n_total)) {
+        s_bad = 1;
+        set_error(&hdr->status, PBIT_EMALFORMED);
+    }
+    __syncthreads();
+    if (s_bad)
+        return;
+    for (int j = 0; j < kBasePer; j++) {
+        uint32_t i = tid + j * kBaseThreads;
+        if (i < m)
+            offn[i] = total - s_val[i];
+    }
+}
+
+// ---------------------------------------------------------------- down
+// Offsets of the members of each chain of level k from the chain's offset.
+__global__ __launch_bounds__(256) void k_down(const uint4* __restrict__ rec_chain,
+                                              const uint32_t* __restrict__ offn_chain,
+                                              uint32_t chain_static, uint32_t chain_cap,
+                                              int level, const uint32_t* __restrict__ members,
+                                              const uint4* __restrict__ rec_elem,
+                                              uint32_t* __restrict__ offn_elem, Header* hdr)
+{
+    if (hdr->status != 0)
+        return;
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t m = chain_static + min(hdr->dyn[level], chain_cap);
+    if (c >= m)
+        return;
+    const uint4 r = rec_chain[c];
+    if (r.y == 0)
+        return;
+    uint32_t off = offn_chain[c];
+    const uint32_t* mem = members + (size_t)c * kSegUp;
+    const uint32_t cnt = min(r.z, kSegUp);
+    for (uint32_t t = 0; t < cnt; t++) {
+        uint32_t j = mem[t];
+        offn_elem[j] = off;
+        off += rec_elem[j].y;
+    }
+}
+
+// ---------------------------------------------------------------- unchain
+// Level-0 segments to list order: keys and node indices at their offsets.
+template <typename KeyT>
+__global__ __launch_bounds__(256) void k_unchain(const uint4* __restrict__ rec_seg,
+                                                 const uint32_t* __restrict__ offn_seg,
+                                                 uint32_t seg_static, uint32_t seg_cap,
+                                                 const Entry<KeyT>* __restrict__ buf, uint32_t n,
+                                                 KeyT* __restrict__ keys_l,
+                                                 uint32_t* __restrict__ idx_l, Header* hdr)
+{
+    if (hdr->status != 0)
+        return;
+    const uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    const uint32_t s = (uint32_t)(g / kSeg0), t = (uint32_t)(g % kSeg0);
+    const uint32_t m = seg_static + min(hdr->dyn[0], seg_cap);
+    if (s >= m)
+        return;
+    const uint4 r = rec_seg[s];
+    if (t >= r.y)
+        return;
+    const uint32_t pos = offn_seg[s] + t;
+    if (pos >= n)
+        return;
+    const Entry<KeyT> e = buf[(size_t)s * kSeg0 + t];
+    keys_l[pos] = entry_key<KeyT>(e);
+    idx_l[pos] = e.idx;
+}
+
+// ---------------------------------------------------------------- schedule
+// Per pass: exclusive scan of the digit counts (global digit bases), whether
+// the pass is the identity, and which ping-pong buffer it reads.
+template <int RB>
+__global__ __launch_bounds__(256) void k_schedule(const uint32_t* __restrict__ hist,
+                                                  uint32_t* __restrict__ dbase, uint32_t passes,
+                                                  uint32_t n, Header* hdr)
+{
+    constexpr uint32_t RADIX = 1u << RB;
+    __shared__ uint32_t s_v[RADIX];
+    __shared__ uint32_t s_skip[kMaxPasses];
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t p = 0; p < passes; p++) {
+        uint32_t v = 0;
+        if (tid < RADIX)
+            v = hist[p * RADIX + tid];
+        if (tid < RADIX)
+            s_v[tid] = v;
+        __syncthreads();
+        int full = (tid < RADIX) && (v == n);
+        int any_full = __syncthreads_or(full);
+        if (tid == 0) {
+            uint32_t sum = 0;
+            for (uint32_t d = 0; d < RADIX; d++) {
+                uint32_t x = s_v[d];
+                s_v[d] = sum;
+                sum += x;
+            }
+            s_skip[p] = any_full ? 1u : 0u;
+        }
+        __syncthreads();
+        if (tid < RADIX)
+            dbase[p * RADIX + tid] = s_v[tid];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        uint32_t cur = 0;
+        int last = -1;
+        for (uint32_t p = 0; p < passes; p++) {
+            PassSched ps;
+            ps.skip = s_skip[p];
+            ps.in_buf = cur;
+            ps.last = 0;
+            ps.pad = 0;
+            if (!ps.skip) {
+                cur ^= 1u;
+                last = (int)p;
+            }
+            hdr->sched[p] = ps;
+        }
+        if (last >= 0)
+            hdr->sched[last].last = 1;
+        hdr->final_buf = cur;
+    }
+}
+
+// ---------------------------------------------------------------- digit pass
+// One stable split on the pattern at bit `shift`: a tile of BLOCK*ITEMS
+// consecutive list positions is ranked in registers and LDS, its per-digit
+// counts are chained across tiles with decoupled look-back (tiles take
+// tickets in order so every tile waits only on tiles already running), and
+// the tile is written out grouped by digit.
+__device__ __forceinline__ uint64_t lanemask_lt()
+{
+    const uint32_t lane = __lane_id();
+    return (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+}
+
+template <typename KeyT, int RB, int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_digit_pass(uint32_t pass, uint32_t shift, uint32_t n,
+                                                      KeyT* __restrict__ keysA,
+                                                      uint32_t* __restrict__ idxA,
+                                                      KeyT* __restrict__ keysB,
+                                                      uint32_t* __restrict__ idxB,
+                                                      const uint32_t* __restrict__ dbase,
+                                                      uint32_t* __restrict__ look, Header* hdr)
+{
+    constexpr uint32_t RADIX = 1u << RB;
+    constexpr uint32_t WAVES = BLOCK / 64;
+    constexpr uint32_t TILE = BLOCK * ITEMS;
+    __shared__ uint32_t s_wave[WAVES][RADIX];
+    __shared__ uint32_t s_count[RADIX];
+    __shared__ uint32_t s_start[RADIX];
+    __shared__ uint32_t s_gbase[RADIX];
+    __shared__ KeyT s_keys[TILE];
+    __shared__ uint32_t s_idx[TILE];
+    __shared__ uint32_t s_tile;
+
+    if (hdr->status != 0)
+        return;
+    const PassSched ps = hdr->sched[pass];
+    if (ps.skip)
+        return;
+    const KeyT* kin = ps.in_buf ? keysB : keysA;
+    const uint32_t* iin = ps.in_buf ? idxB : idxA;
+    KeyT* kout = ps.in_buf ? keysA : keysB;
+    uint32_t* iout = ps.in_buf ? idxA : idxB;
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t wave = tid / 64, lane = tid % 64;
+    for (uint32_t i = tid; i < WAVES * RADIX; i += BLOCK)
+        (&s_wave[0][0])[i] = 0;
+    if (tid == 0)
+        s_tile = atomicAdd(&hdr->tile_ctr[pass], 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint64_t tbase = (uint64_t)tile * TILE;
+    const uint64_t wbase = tbase + (uint64_t)wave * (64 * ITEMS);
+
+    KeyT key[ITEMS];
+    uint32_t idx[ITEMS];
+    uint32_t dig[ITEMS];
+    uint32_t rank[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+        const uint64_t e = wbase + (uint64_t)i * 64 + lane;
+        if (e < n) {
+            key[i] = kin[e];
+            idx[i] = iin[e];
+            dig[i] = (uint32_t)(key[i] >> shift) & (RADIX - 1u);
+        } else {
+            key[i] = 0;
+            idx[i] = 0;
+            dig[i] = RADIX;
+        }
+    }
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+        const bool valid = dig[i] < RADIX;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < RB; b++) {
+            const bool bit = (dig[i] >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            peers &= bit ? bb : ~bb;
+        }
+        if (valid) {
+            const uint32_t below = __popcll(peers & lt);
+            const uint32_t base = s_wave[wave][dig[i]];
+            rank[i] = base + below;
+            if (below == 0)
+                s_wave[wave][dig[i]] = base + __popcll(peers);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // per digit: exclusive offsets across waves and the tile count
+    for (uint32_t d = tid; d < RADIX; d += BLOCK) {
+        uint32_t sum = 0;
+#pragma unroll
+        for (uint32_t w = 0; w < WAVES; w++) {
+            uint32_t v = s_wave[w][d];
+            s_wave[w][d] = sum;
+            sum += v;
+        }
+        s_count[d] = sum;
+        // publish this tile's count early so successors can proceed
+        st_agent(&look[(size_t)tile * RADIX + d], (tile == 0 ? kFlagPrefix : kFlagAgg) | sum);
+    }
+    __syncthreads();
+    // local digit starts (exclusive scan over digits) by wave 0
+    if (wave == 0) {
+        constexpr uint32_t PER = (RADIX + 63) / 64;
+        uint32_t vals[PER];
+        uint32_t local = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < PER; j++) {
+            uint32_t d = lane * PER + j;
+            vals[j] = d < RADIX ? s_count[d] : 0;
+            local += vals[j];
+        }
+        uint32_t incl = local;
+#pragma unroll
+        for (uint32_t off = 1; off < 64; off <<= 1) {
+            uint32_t up = __shfl_up(incl, off, 64);
+            if (lane >= off)
+                incl += up;
+        }
+        uint32_t run = incl - local;
+#pragma unroll
+        for (uint32_t j = 0; j < PER; j++) {
+            uint32_t d = lane * PER + j;
+            if (d < RADIX)
+                s_start[d] = run;
+            run += vals[j];
+        }
+    }
+    // decoupled look-back per digit
+    for (uint32_t d = tid; d < RADIX; d += BLOCK) {
+        uint32_t excl = 0;
+        if (tile != 0) {
+            int64_t j = (int64_t)tile - 1;
+            while (j >= 0) {
+                uint32_t v = ld_agent(&look[(size_t)j * RADIX + d]);
+                uint32_t f = v & ~kCountMask;
+                if (f == 0) {
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                excl += v & kCountMask;
+                if (f == kFlagPrefix)
+                    break;
+                j--;
+            }
+            st_agent(&look[(size_t)tile * RADIX + d], kFlagPrefix | (excl + s_count[d]));
+        }
+        s_gbase[d] = dbase[d] + excl;
+    }
+    __syncthreads();
+    // stage the tile in LDS grouped by digit (stable)
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+        if (dig[i] < RADIX) {
+            const uint32_t pos = s_start[dig[i]] + s_wave[wave][dig[i]] + rank[i];
+            s_keys[pos] = key[i];
+            s_idx[pos] = idx[i];
+        }
+    }
+    __syncthreads();
+    const uint32_t valid_n = (uint32_t)min<uint64_t>((uint64_t)TILE, (uint64_t)n - tbase);
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+        const uint32_t j = tid + i * BLOCK;
+        if (j < valid_n) {
+            const KeyT k = s_keys[j];
+            const uint32_t d = (uint32_t)(k >> shift) & (RADIX - 1u);
+            const uint32_t g = s_gbase[d] + (j - s_start[d]);
+            if (g < n) {
+                if (!ps.last)
+                    kout[g] = k;
+                iout[g] = s_idx[j];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- relink
+// next[order[j]] = order[j+1]; the last node gets NIL; result = {head, status}.
+__global__ __launch_bounds__(256) void k_relink(const uint32_t* __restrict__ idxA,
+                                                const uint32_t* __restrict__ idxB, uint32_t n,
+                                                uint32_t* __restrict__ next_out,
+                                                uint32_t* __restrict__ result, const Header* hdr)
+{
+    const int32_t st = hdr->status;
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (st != 0) {
+        if (j == 0) {
+            result[0] = kNil;
+            result[1] = (uint32_t)st;
+        }
+        return;
+    }
+    const uint32_t* order = hdr->final_buf ? idxB : idxA;
+    if (j < n) {
+        const uint32_t node = order[j];
+        const uint32_t succ = (j + 1 < n) ? order[j + 1] : kNil;
+        if (node < n)
+            next_out[node] = succ;
+        if (j == 0) {
+            result[0] = node;
+            result[1] = 0;
+        }
+    }
+}
+
+__global__ void k_empty_result(uint32_t* result)
+{
+    result[0] = kNil;
+    result[1] = 0;
+}
+
+// ---------------------------------------------------------------- launch helpers
+template <typename KeyT>
+struct Launcher {
+    static hipError_t pack(const Plan& P, const uint32_t* next, const void* keys, char* ws,
+                           hipStream_t s);
+    static hipError_t walk0(const Plan& P, uint32_t head, char* ws, hipStream_t s);
+    static hipError_t unchain(const Plan& P, char* ws, hipStream_t s);
+    static hipError_t passes(const Plan& P, char* ws, hipStream_t s);
+};
+
+template <typename KeyT, int RB>
+static hipError_t launch_pack_rb(const Plan& P, const uint32_t* next, const void* keys,
+                                 char* ws, hipStream_t s)
+{
+    KeyT mask = 0;
+    if (P.flags & PBIT_SIGNED)
+        mask ^= (KeyT)((KeyT)1 << (sizeof(KeyT) * 8 - 1));
+    if (P.flags & PBIT_DESCENDING)
+        mask ^= (KeyT)~(KeyT)0;
+    uint64_t want = (P.n + 255) / 256;
+    uint32_t blocks = (uint32_t)(want < 1024 ? want : 1024);
+    size_t shm = (size_t)P.passes * P.radix * sizeof(uint32_t);
+    hipLaunchKernelGGL((k_pack<KeyT, RB>), dim3(blocks), dim3(256), shm, s, next,
+                       (const KeyT*)keys, (uint32_t)P.n, mask, P.passes,
+                       (NodeRec<KeyT>*)(ws + P.o_nodes), (uint32_t*)(ws + P.o_hist),
+                       (Header*)(ws + P.o_header));
+    return hipGetLastError();
+}
+
+template <typename KeyT, int RB>
+static hipError_t launch_passes_rb(const Plan& P, char* ws, hipStream_t s)
+{
+    constexpr int BLOCK = 256;
+    constexpr int ITEMS = sizeof(KeyT) == 8 ? 8 : 16;
+    constexpr uint32_t RADIX = 1u << RB;
+    hipLaunchKernelGGL((k_schedule<RB>), dim3(1), dim3(256), 0, s,
+                       (const uint32_t*)(ws + P.o_hist), (uint32_t*)(ws + P.o_dbase), P.passes,
+                       (uint32_t)P.n, (Header*)(ws + P.o_header));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    for (uint32_t p = 0; p < P.passes; p++) {
+        uint32_t* look = (uint32_t*)(ws + P.o_look) + (size_t)p * P.tiles * RADIX;
+        hipLaunchKernelGGL((k_digit_pass<KeyT, RB, BLOCK, ITEMS>), dim3(P.tiles), dim3(BLOCK), 0,
+                           s, p, p * RB, (uint32_t)P.n, (KeyT*)(ws + P.o_keysA),
+                           (uint32_t*)(ws + P.o_idxA), (KeyT*)(ws + P.o_keysB),
+                           (uint32_t*)(ws + P.o_idxB),
+                           (const uint32_t*)(ws + P.o_dbase) + (size_t)p * RADIX, look,
+                           (Header*)(ws + P.o_header));
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+template <typename KeyT>
+hipError_t Launcher<KeyT>::pack(const Plan& P, const uint32_t* next, const void* keys, char* ws,
+                                hipStream_t s)
+{
+    switch (P.RB) {
+    case 1: return launch_pack_rb<KeyT, 1>(P, next, keys, ws, s);
+    case 2: return launch_pack_rb<KeyT, 2>(P, next, keys, ws, s);
+    case 4: return launch_pack_rb<KeyT, 4>(P, next, keys, ws, s);
+    default: return launch_pack_rb<KeyT, 8>(P, next, keys, ws, s);
+    }
+}
+
+template <typename KeyT>
+hipError_t Launcher<KeyT>::passes(const Plan& P, char* ws, hipStream_t s)
+{
+    switch (P.RB) {
+    case 1: return launch_passes_rb<KeyT, 1>(P, ws, s);
+    case 2: return launch_passes_rb<KeyT, 2>(P, ws, s);
+    case 4: return launch_passes_rb<KeyT, 4>(P, ws, s);
+    default: return launch_passes_rb<KeyT, 8>(P, ws, s);
+    }
+}
+
+template <typename KeyT>
+hipError_t Launcher<KeyT>::walk0(const Plan& P, uint32_t head, char* ws, hipStream_t s)
+{
+    const LevelPlan& L = P.lv[0];
+    uint32_t blocks = (uint32_t)((L.n_static + 255) / 256);
+    hipLaunchKernelGGL((k_walk0<KeyT>), dim3(blocks), dim3(256), 0, s,
+                       (const NodeRec<KeyT>*)(ws + P.o_nodes), (uint32_t)P.n, head,
+                       (uint32_t)L.n_static, (uint32_t)L.dyn_cap, (uint4*)(ws + L.o_rec_out),
+                       (Entry<KeyT>*)(ws + L.o_members), (Header*)(ws + P.o_header));
+    return hipGetLastError();
+}
+
+template <typename KeyT>
+hipError_t Launcher<KeyT>::unchain(const Plan& P, char* ws, hipStream_t s)
+{
+    const LevelPlan& L = P.lv[0];
+    uint64_t threads = L.out_bound * kSeg0;
+    uint32_t blocks = (uint32_t)((threads + 255) / 256);
+    hipLaunchKernelGGL((k_unchain<KeyT>), dim3(blocks), dim3(256), 0, s,
+                       (const uint4*)(ws + L.o_rec_out), (const uint32_t*)(ws + L.o_offn_out),
+                       (uint32_t)L.n_static, (uint32_t)L.dyn_cap,
+                       (const Entry<KeyT>*)(ws + L.o_members), (uint32_t)P.n,
+                       (KeyT*)(ws + P.o_keysA), (uint32_t*)(ws + P.o_idxA),
+                       (Header*)(ws + P.o_header));
+    return hipGetLastError();
+}
+
+size_t entry_bytes(uint32_t key_bytes) { return key_bytes == 8 ? 16 : 8; }
+size_t node_bytes(uint32_t key_bytes) { return key_bytes == 8 ? 16 : 8; }
+
+// Everything after the plan: the whole path queued on one stream.
+hipError_t enqueue_sort(const Plan& P, uint32_t head, const uint32_t* next_in, uint32_t* next_out,
+                        const void* keys, uint32_t* d_result, char* ws, hipStream_t s)
+{
+    hipError_t e;
+    {
+        size_t words = (P.zero_end - P.o_header) / 4;
+        size_t want = (words + 255) / 256;
+        uint32_t blocks = (uint32_t)(want < 2048 ? want : 2048);
+        hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, (uint32_t*)(ws + P.o_header),
+                           words);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+    }
+    switch (P.key_bytes) {
+    case 1: e = Launcher<uint8_t>::pack(P, next_in, keys, ws, s); break;
+    case 2: e = Launcher<uint16_t>::pack(P, next_in, keys, ws, s); break;
+    case 4: e = Launcher<uint32_t>::pack(P, next_in, keys, ws, s); break;
+    default: e = Launcher<uint64_t>::pack(P, next_in, keys, ws, s); break;
+    }
+    if (e != hipSuccess)
+        return e;
+    switch (P.key_bytes) {
+    case 1: e = Launcher<uint8_t>::walk0(P, head, ws, s); break;
+    case 2: e = Launcher<uint16_t>::walk0(P, head, ws, s); break;
+    case 4: e = Launcher<uint32_t>::walk0(P, head, ws, s); break;
+    default: e = Launcher<uint64_t>::walk0(P, head, ws, s); break;
+    }
+    if (e != hipSuccess)
+        return e;
+    Header* hdr = (Header*)(ws + P.o_header);
+    for (int k = 1; k < P.levels; k++) {
+        const LevelPlan& L = P.lv[k];
+        const LevelPlan& Lp = P.lv[k - 1];
+        uint32_t blocks = (uint32_t)((L.n_static + 255) / 256);
+        hipLaunchKernelGGL(k_walk_up, dim3(blocks), dim3(256), 0, s,
+                           (const uint4*)(ws + Lp.o_rec_out), (uint32_t)Lp.n_static,
+                           (uint32_t)Lp.dyn_cap, k - 1, (uint32_t)L.n_static,
+                           (uint32_t)L.dyn_cap, k, (uint4*)(ws + L.o_rec_out),
+                           (uint32_t*)(ws + L.o_members), hdr);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+    }
+    {
+        const LevelPlan& Lt = P.lv[P.levels - 1];
+        hipLaunchKernelGGL(k_base, dim3(1), dim3(kBaseThreads), 0, s,
+                           (const uint4*)(ws + Lt.o_rec_out), (uint32_t)Lt.n_static,
+                           (uint32_t)Lt.dyn_cap, P.levels - 1, (uint32_t)P.n,
+                           (uint32_t*)(ws + Lt.o_offn_out), hdr);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+    }
+    for (int k = P.levels - 1; k >= 1; k--) {
+        const LevelPlan& L = P.lv[k];       // chains of level k = elements of level k+1
+        const LevelPlan& Lp = P.lv[k - 1];  // elements of level k
+        uint32_t blocks = (uint32_t)((L.out_bound + 255) / 256);
+        hipLaunchKernelGGL(k_down, dim3(blocks), dim3(256), 0, s,
+                           (const uint4*)(ws + L.o_rec_out), (const uint32_t*)(ws + L.o_offn_out),
+                           (uint32_t)L.n_static, (uint32_t)L.dyn_cap, k,
+                           (const uint32_t*)(ws + L.o_members), (const uint4*)(ws + Lp.o_rec_out),
+                           (uint32_t*)(ws + Lp.o_offn_out), hdr);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+    }
+    switch (P.key_bytes) {
+    case 1: e = Launcher<uint8_t>::unchain(P, ws, s); break;
+    case 2: e = Launcher<uint16_t>::unchain(P, ws, s); break;
+    case 4: e = Launcher<uint32_t>::unchain(P, ws, s); break;
+    default: e = Launcher<uint64_t>::unchain(P, ws, s); break;
+    }
+    if (e != hipSuccess)
+        return e;
+    switch (P.key_bytes) {
+    case 1: e = Launcher<uint8_t>::passes(P, ws, s); break;
+    case 2: e = Launcher<uint16_t>::passes(P, ws, s); break;
+    case 4: e = Launcher<uint32_t>::passes(P, ws, s); break;
+    default: e = Launcher<uint64_t>::passes(P, ws, s); break;
+    }
+    if (e != hipSuccess)
+        return e;
+    {
+        uint32_t blocks = (uint32_t)((P.n + 255) / 256);
+        hipLaunchKernelGGL(k_relink, dim3(blocks), dim3(256), 0, s,
+                           (const uint32_t*)(ws + P.o_idxA), (const uint32_t*)(ws + P.o_idxB),
+                           (uint32_t)P.n, next_out, d_result, (const Header*)hdr);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t enqueue_empty(uint32_t* d_result, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_empty_result, dim3(1), dim3(1), 0, s, d_result);
+    return hipGetLastError();
+}
+
+}  // namespace pbit

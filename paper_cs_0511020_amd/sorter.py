@@ -1,0 +1,83 @@
+"""Device-resident list sorting on top of the C ABI.
+
+``ListSorter`` owns a workspace and a result word on one device and sorts
+lists held in torch device tensors (``next`` uint32 as int32 storage, keys of
+8/16/32/64 bits).  Every step runs in libpbit's HIP kernels; this module only
+allocates device memory through torch and passes pointers.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _lib
+
+_KEY_BITS = {torch.uint8: 8, torch.int8: 8, torch.int16: 16, torch.uint16: 16,
+             torch.int32: 32, torch.uint32: 32, torch.int64: 64, torch.uint64: 64}
+
+
+def key_bits(keys: torch.Tensor) -> int:
+    try:
+        return _KEY_BITS[keys.dtype]
+    except KeyError:
+        raise TypeError("unsupported key dtype %s" % keys.dtype) from None
+
+
+class PbitError(RuntimeError):
+    def __init__(self, code: int):
+        super().__init__("%s (%d)" % (_lib.status_string(code), code))
+        self.code = code
+
+
+class ListSorter:
+    """Sort singly-linked lists stored as device arrays.
+
+    next: int32/uint32 tensor of n node indices (0xFFFFFFFF ends the list).
+    keys: n unsigned (or, with ``signed=True``, two's-complement) integers.
+    """
+
+    def __init__(self, device="cuda"):
+        self.device = torch.device(device)
+        self._ws = None
+        self._ws_bytes = 0
+        self.result = torch.zeros(2, dtype=torch.int32, device=self.device)
+
+    def workspace(self, n: int, M: int, K: int = 0) -> torch.Tensor:
+        need = _lib.workspace_bytes(n, M, K)
+        if need == 0:
+            raise PbitError(_lib.EINVAL)
+        if self._ws is None or self._ws_bytes < need:
+            self._ws = None
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+            self._ws_bytes = need
+        return self._ws
+
+    def sort_async(self, head: int, next_in: torch.Tensor, keys: torch.Tensor, K: int = 0,
+                   descending: bool = False, signed: bool = False,
+                   next_out: torch.Tensor | None = None, result: torch.Tensor | None = None,
+                   stream=None) -> torch.Tensor:
+        """Queue the sort; returns the 2-word device result {head, status}."""
+        n = int(next_in.numel())
+        M = key_bits(keys)
+        if int(keys.numel()) != n:
+            raise ValueError("keys and next differ in length")
+        if next_out is None:
+            next_out = next_in
+        if result is None:
+            result = self.result
+        ws = self.workspace(n, M, K)
+        flags = (_lib.DESCENDING if descending else 0) | (_lib.SIGNED if signed else 0)
+        st = _lib.sort_list_async(head, next_in, next_out, keys, n, M, K, flags, result, ws,
+                                  self._ws_bytes, stream)
+        if st != _lib.OK:
+            raise PbitError(st)
+        return result
+
+    def sort(self, head: int, next_in: torch.Tensor, keys: torch.Tensor, K: int = 0,
+             descending: bool = False, signed: bool = False,
+             next_out: torch.Tensor | None = None) -> int:
+        """Sort and wait; returns the new head (0xFFFFFFFF if empty)."""
+        res = self.sort_async(head, next_in, keys, K, descending, signed, next_out)
+        h, st = (int(x) for x in res.cpu().tolist())
+        if st != 0:
+            raise PbitError(st)
+        return h & 0xFFFFFFFF

@@ -1,0 +1,90 @@
+"""The C-ABI library loads and exports every declared symbol; host-side
+argument checks reject bad calls before any device work (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_cs_0511020_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_cs_0511020_amd import build
+        build.build()
+    return _lib.load()
+
+
+def declared_functions():
+    names = []
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if not h.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"\b(pbit_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert "pbit_sort_list_async" in names and "pbit_sort_list" in names
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in _lib._SIGNATURES, "binding misses " + name
+
+
+def test_version_and_status_strings(lib):
+    assert "gfx950" in _lib.version()
+    for code in (0, -1, -2, -3, -4):
+        assert _lib.status_string(code) != "unknown status"
+
+
+def test_workspace_bytes_shapes(lib):
+    assert _lib.workspace_bytes(1 << 16, 32, 4) > (1 << 16) * 16
+    assert _lib.workspace_bytes(1 << 16, 32, 0) > 0
+    for M, K in [(8, 1), (8, 2), (8, 4), (8, 8), (16, 8), (64, 4), (64, 8)]:
+        assert _lib.workspace_bytes(1000, M, K) > 0
+    # rejected shapes
+    assert _lib.workspace_bytes(1000, 12, 4) == 0
+    assert _lib.workspace_bytes(1000, 32, 3) == 0
+    assert _lib.workspace_bytes(1000, 32, 16) == 0
+    assert _lib.workspace_bytes(1000, 8, 16) == 0
+    assert _lib.workspace_bytes(1 << 30, 32, 4) == 0
+    # the workspace grows linearly with n
+    a, b = _lib.workspace_bytes(1 << 20, 32, 8), _lib.workspace_bytes(1 << 21, 32, 8)
+    assert 1.8 < b / a < 2.2
+
+
+def _call(lib, head=0, nxt=0x1000, nout=0x1000, keys=0x1000, n=8, M=32, K=4, flags=0,
+          res=0x2000, ws=0x100000, ws_bytes=1 << 40):
+    return lib.pbit_sort_list_async(head, nxt, nout, keys, n, M, K, flags, res, ws, ws_bytes,
+                                    None)
+
+
+def test_host_argument_checks(lib):
+    E = _lib.EINVAL
+    assert _call(lib, M=12) == E
+    assert _call(lib, K=3) == E
+    assert _call(lib, M=8, K=16) == E
+    assert _call(lib, flags=8) == E
+    assert _call(lib, res=0) == E
+    assert _call(lib, res=0x2002) == E            # misaligned result
+    assert _call(lib, head=8, n=8) == E           # head out of range
+    assert _call(lib, head=_lib.NIL, n=8) == E    # empty head with nodes
+    assert _call(lib, nxt=0) == E
+    assert _call(lib, keys=0) == E
+    assert _call(lib, ws=0) == E
+    assert _call(lib, keys=0x1002, M=32) == E     # misaligned keys
+    assert _call(lib, ws=0x100010) == E           # misaligned workspace
+    assert _call(lib, n=1 << 30) == E
+    assert _call(lib, ws_bytes=16) == _lib.ENOMEM
+    # the synchronous form checks the same way before touching a device
+    assert lib.pbit_sort_list(0, 0x1000, 0x1000, 8, 12, 4) == E
+    assert lib.pbit_sort_list(9, 0x1000, 0x1000, 8, 32, 4) == E
+    assert lib.pbit_sort_list(0, 0, 0x1000, 8, 32, 4) == E
+    assert lib.pbit_sort_list(_lib.NIL, 0, 0, 0, 32, 4) == _lib.NIL

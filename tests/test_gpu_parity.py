@@ -1,0 +1,191 @@
+"""GPU parity: the HIP path against the CPU oracle, bit-exact (identical
+relinked next[] and head), on seeded inputs."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_cs_0511020_amd import inputs
+
+from .gpu_util import NIL, check_properties, definition_order, gpu_sort, oracle_flags
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_cs_0511020_amd import _lib
+    _lib.load()
+
+
+def run_parity(oracle_mod, head, nxt, keys, K, flags=0, inplace=True):
+    M = keys.dtype.itemsize * 8
+    h, st, got = gpu_sort(head, nxt, keys, K, flags, inplace)
+    Keff = K if K else (4 if M == 8 else 8)
+    eh, enext = oracle_mod.sort_list(head, nxt, keys, M, Keff, flags=oracle_flags(flags, oracle_mod))
+    assert st == 0
+    assert h == eh
+    assert np.array_equal(got, enext)
+
+
+def test_worked_example(oracle_mod):
+    with open(os.path.join(HERE, "golden", "worked_example.json")) as f:
+        g = json.load(f)
+    keys = np.array(g["keys_in_list_order"], dtype=np.uint8)
+    nxt, head = inputs.links_from_order(np.arange(8))
+    for K in (4, 8, 2, 1):
+        say("worked example K=%d" % K)
+        h, st, got = gpu_sort(head, nxt, keys, K)
+        assert st == 0 and h == g["ascending_head"] and got.tolist() == g["ascending_next"]
+    h, st, got = gpu_sort(head, nxt, keys, 4, flags=1)
+    assert h == g["descending_head"] and got.tolist() == g["descending_next"]
+
+
+@pytest.mark.parametrize("K", [4, 8])
+def test_c1_uniform_u32_65536(oracle_mod, K):
+    say("C1 K=%d" % K)
+    rng = inputs.rng_for(1001)
+    n = 65536
+    nxt, head, _ = inputs.random_list(n, rng)
+    keys = inputs.uniform_keys(n, 32, rng)
+    run_parity(oracle_mod, head, nxt, keys, K)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 15, 16, 17, 255, 4095, 4096, 4097, 8191, 40000, 70001,
+                               262147])
+def test_sizes_ragged(oracle_mod, n):
+    say("ragged n=%d" % n)
+    rng = inputs.rng_for(7000 + n)
+    nxt, head, _ = inputs.random_list(n, rng)
+    keys = rng.integers(0, 1 << 12, size=n).astype(np.uint32) * np.uint32(977)
+    run_parity(oracle_mod, head, nxt, keys, 4)
+    run_parity(oracle_mod, head, nxt, keys, 8, inplace=False)
+
+
+@pytest.mark.parametrize("M", [8, 16, 32, 64])
+@pytest.mark.parametrize("K", [1, 2, 4, 8])
+def test_key_widths_and_patterns(oracle_mod, M, K):
+    if M % K:
+        pytest.skip()
+    say("M=%d K=%d" % (M, K))
+    rng = inputs.rng_for(300 + M * 10 + K)
+    n = 20011
+    nxt, head, _ = inputs.random_list(n, rng)
+    keys = inputs.uniform_keys(n, M, rng)
+    keys[::7] = keys[3]  # duplicates
+    run_parity(oracle_mod, head, nxt, keys, K)
+
+
+@pytest.mark.parametrize("dist", ["uniform", "zipf", "distinct8"])
+def test_c2_distributions_reduced(oracle_mod, dist):
+    say("C2 shape reduced %s" % dist)
+    rng = inputs.rng_for({"uniform": 2001, "zipf": 2002, "distinct8": 2003}[dist])
+    n = 1 << 18
+    nxt, head, _ = inputs.random_list(n, rng)
+    keys = inputs.c2_keys(dist, n, rng)
+    for K in (4, 8):
+        run_parity(oracle_mod, head, nxt, keys, K)
+
+
+@pytest.mark.parametrize("flags", [1, 2, 3])
+def test_descending_signed(oracle_mod, flags):
+    rng = inputs.rng_for(50 + flags)
+    for M in (8, 16, 32, 64):
+        say("flags=%d M=%d" % (flags, M))
+        n = 9000
+        nxt, head, _ = inputs.random_list(n, rng)
+        keys = inputs.uniform_keys(n, M, rng)
+        keys[::5] = keys[1]
+        run_parity(oracle_mod, head, nxt, keys, 4, flags=flags)
+
+
+def test_special_layouts(oracle_mod):
+    rng = inputs.rng_for(61)
+    n = 50000
+    say("identity layout")
+    nxt, head, _ = inputs.identity_list(n)
+    keys = rng.integers(0, 100, size=n).astype(np.uint32)
+    run_parity(oracle_mod, head, nxt, keys, 8)
+    say("all keys equal")
+    nxt, head, _ = inputs.random_list(n, rng)
+    keys = np.full(n, 12345, dtype=np.uint32)
+    h, st, got = gpu_sort(head, nxt, keys, 4)
+    assert st == 0 and h == head and np.array_equal(got, nxt)
+    say("already sorted")
+    order = rng.permutation(n).astype(np.uint32)
+    nxt, head = inputs.links_from_order(order)
+    keys = np.empty(n, dtype=np.uint32)
+    keys[order] = np.sort(inputs.uniform_keys(n, 32, rng))
+    h, st, got = gpu_sort(head, nxt, keys, 8)
+    assert st == 0 and h == head and np.array_equal(got, nxt)
+    say("paper-shape keys (top 17 bits constant)")
+    nxt, head, _ = inputs.random_list(n, rng)
+    keys = rng.integers(0, 1 << 15, size=n).astype(np.uint32)
+    run_parity(oracle_mod, head, nxt, keys, 4)
+
+
+def test_malformed_lists_are_rejected_untouched():
+    rng = inputs.rng_for(71)
+    n = 30000
+    nxt, head, order = inputs.random_list(n, rng)
+    keys = inputs.uniform_keys(n, 32, rng)
+    cases = {}
+    bad = nxt.copy(); bad[order[n // 2]] = order[n // 3]; cases["cycle"] = bad
+    bad = nxt.copy(); bad[order[100]] = n + 5; cases["index out of range"] = bad
+    bad = nxt.copy(); bad[order[n - 10]] = NIL; cases["short list"] = bad
+    bad = nxt.copy(); bad[order[-1]] = order[0]; cases["cycle through head"] = bad
+    for name, b in cases.items():
+        say("malformed:", name)
+        h, st, got = gpu_sort(head, b, keys, 8)
+        assert st == -2, name
+        assert h == NIL
+        assert np.array_equal(got, b), name
+
+
+def test_empty_list():
+    import torch
+    from paper_cs_0511020_amd.sorter import ListSorter
+    s = ListSorter()
+    nt = torch.zeros(0, dtype=torch.int32, device="cuda")
+    kt = torch.zeros(0, dtype=torch.int32, device="cuda")
+    assert s.sort(NIL, nt, kt, 4) == NIL
+
+
+def test_sync_entry_point_in_place(oracle_mod):
+    import torch
+    from paper_cs_0511020_amd import _lib
+    from .gpu_util import from_dev, to_dev
+    rng = inputs.rng_for(81)
+    n = 100000
+    nxt, head, _ = inputs.random_list(n, rng)
+    keys = inputs.uniform_keys(n, 16, rng)
+    nt, kt = to_dev(nxt, torch), to_dev(keys, torch)
+    torch.cuda.synchronize()
+    h = _lib.sort_list(head, nt, kt, 16, 4)
+    eh, enext = oracle_mod.sort_list(head, nxt, keys, 16, 4)
+    assert h == eh and np.array_equal(from_dev(nt), enext)
+
+
+@pytest.mark.parametrize("dist", ["uniform", "zipf", "distinct8"])
+def test_c2_full_size_properties(oracle_mod, dist):
+    """n = 2^24 in the benchmark's configuration: the properties that fix
+    the stable sort, plus the exact definition (numpy stable argsort)."""
+    say("C2 full %s" % dist)
+    rng = inputs.rng_for({"uniform": 2001, "zipf": 2002, "distinct8": 2003}[dist])
+    n = 1 << 24
+    nxt, head, order = inputs.random_list(n, rng)
+    keys = inputs.c2_keys(dist, n, rng)
+    for K in (8, 4):
+        h, st, got = gpu_sort(head, nxt, keys, K, inplace=False)
+        assert st == 0
+        out = check_properties(h, got, keys, order, oracle_mod.list_order)
+        assert np.array_equal(out, definition_order(order, keys))
