@@ -95,6 +95,26 @@ int pbit_sort_list_async(uint32_t head, const uint32_t *next_in, uint32_t *next_
 int64_t pbit_sort_list(uint32_t head, uint32_t *next, const void *keys, uint64_t n,
                        uint32_t M, uint32_t K);
 
+/*
+ * Measurement form of pbit_sort_list_async (same arguments and result):
+ * events[0..n_events) are hipEvent_t handles created by the caller; the
+ * library records events[i] on `stream` before the i-th kernel stage it
+ * queues and one more after the last, stores the stage id of each interval
+ * in stage_ids (may be NULL) and the number of events recorded in
+ * *n_recorded.  Stages beyond n_events - 1 are queued but not bracketed.
+ * Used by the benchmark to time each kernel on the stream it runs on.
+ */
+int pbit_sort_list_profiled(uint32_t head, const uint32_t *next_in, uint32_t *next_out,
+                            const void *keys, uint64_t n, uint32_t M, uint32_t K,
+                            uint32_t flags, uint32_t *d_result, void *ws, size_t ws_bytes,
+                            void *stream, void **events, int32_t *stage_ids, int n_events,
+                            int *n_recorded);
+
+/* Name of a stage id reported by pbit_sort_list_profiled ("pack", "walk0",
+ * "walk_up", "base", "down", "unchain", "schedule", "digit_pass", "relink",
+ * "end"). */
+const char *pbit_stage_name(int stage);
+
 /* Human-readable text for a status code. */
 const char *pbit_status_string(int code);
 

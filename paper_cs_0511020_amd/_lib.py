@@ -27,6 +27,12 @@ _SIGNATURES = {
     "pbit_sort_list": (ctypes.c_int64, [
         ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
         ctypes.c_uint32]),
+    "pbit_sort_list_profiled": (ctypes.c_int, [
+        ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+        ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
+        ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+        ctypes.POINTER(ctypes.c_int)]),
+    "pbit_stage_name": (ctypes.c_char_p, [ctypes.c_int]),
     "pbit_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "pbit_version": (ctypes.c_char_p, []),
 }

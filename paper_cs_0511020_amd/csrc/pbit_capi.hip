@@ -12,7 +12,7 @@
 namespace pbit {
 
 hipError_t enqueue_sort(const Plan& P, uint32_t head, const uint32_t* next_in, uint32_t* next_out,
-                        const void* keys, uint32_t* d_result, char* ws, hipStream_t s);
+                        const void* keys, uint32_t* d_result, char* ws, hipStream_t s, Prof* prof);
 hipError_t enqueue_empty(uint32_t* d_result, hipStream_t s);
 size_t entry_bytes(uint32_t key_bytes);
 size_t node_bytes(uint32_t key_bytes);
@@ -132,10 +132,10 @@ extern "C" size_t pbit_workspace_bytes(uint64_t n, uint32_t M, uint32_t K)
     return P.total;
 }
 
-extern "C" int pbit_sort_list_async(uint32_t head, const uint32_t* next_in, uint32_t* next_out,
-                                    const void* keys, uint64_t n, uint32_t M, uint32_t K,
-                                    uint32_t flags, uint32_t* d_result, void* ws,
-                                    size_t ws_bytes, void* stream)
+static int sort_list_async_impl(uint32_t head, const uint32_t* next_in, uint32_t* next_out,
+                                const void* keys, uint64_t n, uint32_t M, uint32_t K,
+                                uint32_t flags, uint32_t* d_result, void* ws, size_t ws_bytes,
+                                void* stream, Prof* prof)
 {
     hipStream_t s = (hipStream_t)stream;
     if (!d_result || ((uintptr_t)d_result & 3u))
@@ -157,8 +157,42 @@ extern "C" int pbit_sort_list_async(uint32_t head, const uint32_t* next_in, uint
         return PBIT_EINVAL;
     if (ws_bytes < P.total)
         return PBIT_ENOMEM;
-    hipError_t e = enqueue_sort(P, head, next_in, next_out, keys, d_result, (char*)ws, s);
+    hipError_t e = enqueue_sort(P, head, next_in, next_out, keys, d_result, (char*)ws, s, prof);
     return e == hipSuccess ? PBIT_OK : PBIT_EHIP;
+}
+
+extern "C" int pbit_sort_list_async(uint32_t head, const uint32_t* next_in, uint32_t* next_out,
+                                    const void* keys, uint64_t n, uint32_t M, uint32_t K,
+                                    uint32_t flags, uint32_t* d_result, void* ws,
+                                    size_t ws_bytes, void* stream)
+{
+    return sort_list_async_impl(head, next_in, next_out, keys, n, M, K, flags, d_result, ws,
+                                ws_bytes, stream, nullptr);
+}
+
+extern "C" int pbit_sort_list_profiled(uint32_t head, const uint32_t* next_in,
+                                       uint32_t* next_out, const void* keys, uint64_t n,
+                                       uint32_t M, uint32_t K, uint32_t flags,
+                                       uint32_t* d_result, void* ws, size_t ws_bytes,
+                                       void* stream, void** events, int32_t* stage_ids,
+                                       int n_events, int* n_recorded)
+{
+    if (!events || n_events <= 0 || !n_recorded)
+        return PBIT_EINVAL;
+    Prof prof{events, stage_ids, n_events, 0};
+    int st = sort_list_async_impl(head, next_in, next_out, keys, n, M, K, flags, d_result, ws,
+                                  ws_bytes, stream, &prof);
+    *n_recorded = prof.count;
+    return st;
+}
+
+extern "C" const char* pbit_stage_name(int stage)
+{
+    static const char* names[] = {"zero", "pack", "walk0", "walk_up", "base", "down",
+                                  "unchain", "schedule", "digit_pass", "relink", "end"};
+    if (stage < 0 || stage > (int)kStageCount)
+        return "unknown";
+    return names[stage];
 }
 
 extern "C" int64_t pbit_sort_list(uint32_t head, uint32_t* next, const void* keys, uint64_t n,

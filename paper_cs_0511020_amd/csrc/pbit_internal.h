@@ -53,6 +53,21 @@ struct LevelPlan {
     size_t o_offn_out;    // node offsets of the level-above elements (u32)
 };
 
+// Stages of one sort, in launch order (measurement hooks name them).
+enum Stage : int32_t {
+    kStageZero = 0, kStagePack, kStageWalk0, kStageWalkUp, kStageBase, kStageDown,
+    kStageUnchain, kStageSchedule, kStagePass, kStageRelink, kStageCount
+};
+
+// Optional event recording between stages: events[i] is recorded before the
+// i-th launched stage, and one more after the last stage.
+struct Prof {
+    void** events;   // hipEvent_t handles owned by the caller
+    int32_t* ids;    // stage id of each recorded interval
+    int n_events;
+    int count;
+};
+
 struct Plan {
     uint64_t n;
     uint32_t M, K, RB, radix, passes, flags, key_bytes;

@@ -682,7 +682,7 @@ struct Launcher {
                            hipStream_t s);
     static hipError_t walk0(const Plan& P, uint32_t head, char* ws, hipStream_t s);
     static hipError_t unchain(const Plan& P, char* ws, hipStream_t s);
-    static hipError_t passes(const Plan& P, char* ws, hipStream_t s);
+    static hipError_t passes(const Plan& P, char* ws, hipStream_t s, Prof* prof);
 };
 
 template <typename KeyT, int RB>
@@ -704,12 +704,15 @@ static hipError_t launch_pack_rb(const Plan& P, const uint32_t* next, const void
     return hipGetLastError();
 }
 
+static inline void mark(Prof* prof, hipStream_t s, int32_t stage);
+
 template <typename KeyT, int RB>
-static hipError_t launch_passes_rb(const Plan& P, char* ws, hipStream_t s)
+static hipError_t launch_passes_rb(const Plan& P, char* ws, hipStream_t s, Prof* prof)
 {
     constexpr int BLOCK = 256;
     constexpr int ITEMS = sizeof(KeyT) == 8 ? 8 : 16;
     constexpr uint32_t RADIX = 1u << RB;
+    mark(prof, s, kStageSchedule);
     hipLaunchKernelGGL((k_schedule<RB>), dim3(1), dim3(256), 0, s,
                        (const uint32_t*)(ws + P.o_hist), (uint32_t*)(ws + P.o_dbase), P.passes,
                        (uint32_t)P.n, (Header*)(ws + P.o_header));
@@ -718,6 +721,7 @@ static hipError_t launch_passes_rb(const Plan& P, char* ws, hipStream_t s)
         return e;
     for (uint32_t p = 0; p < P.passes; p++) {
         uint32_t* look = (uint32_t*)(ws + P.o_look) + (size_t)p * P.tiles * RADIX;
+        mark(prof, s, kStagePass);
         hipLaunchKernelGGL((k_digit_pass<KeyT, RB, BLOCK, ITEMS>), dim3(P.tiles), dim3(BLOCK), 0,
                            s, p, p * RB, (uint32_t)P.n, (KeyT*)(ws + P.o_keysA),
                            (uint32_t*)(ws + P.o_idxA), (KeyT*)(ws + P.o_keysB),
@@ -744,13 +748,13 @@ hipError_t Launcher<KeyT>::pack(const Plan& P, const uint32_t* next, const void*
 }
 
 template <typename KeyT>
-hipError_t Launcher<KeyT>::passes(const Plan& P, char* ws, hipStream_t s)
+hipError_t Launcher<KeyT>::passes(const Plan& P, char* ws, hipStream_t s, Prof* prof)
 {
     switch (P.RB) {
-    case 1: return launch_passes_rb<KeyT, 1>(P, ws, s);
-    case 2: return launch_passes_rb<KeyT, 2>(P, ws, s);
-    case 4: return launch_passes_rb<KeyT, 4>(P, ws, s);
-    default: return launch_passes_rb<KeyT, 8>(P, ws, s);
+    case 1: return launch_passes_rb<KeyT, 1>(P, ws, s, prof);
+    case 2: return launch_passes_rb<KeyT, 2>(P, ws, s, prof);
+    case 4: return launch_passes_rb<KeyT, 4>(P, ws, s, prof);
+    default: return launch_passes_rb<KeyT, 8>(P, ws, s, prof);
     }
 }
 
@@ -784,11 +788,22 @@ hipError_t Launcher<KeyT>::unchain(const Plan& P, char* ws, hipStream_t s)
 size_t entry_bytes(uint32_t key_bytes) { return key_bytes == 8 ? 16 : 8; }
 size_t node_bytes(uint32_t key_bytes) { return key_bytes == 8 ? 16 : 8; }
 
+static inline void mark(Prof* prof, hipStream_t s, int32_t stage)
+{
+    if (!prof || prof->count >= prof->n_events)
+        return;
+    hipEventRecord((hipEvent_t)prof->events[prof->count], s);
+    if (prof->ids)
+        prof->ids[prof->count] = stage;
+    prof->count++;
+}
+
 // Everything after the plan: the whole path queued on one stream.
 hipError_t enqueue_sort(const Plan& P, uint32_t head, const uint32_t* next_in, uint32_t* next_out,
-                        const void* keys, uint32_t* d_result, char* ws, hipStream_t s)
+                        const void* keys, uint32_t* d_result, char* ws, hipStream_t s, Prof* prof)
 {
     hipError_t e;
+    mark(prof, s, kStageZero);
     {
         size_t words = (P.zero_end - P.o_header) / 4;
         size_t want = (words + 255) / 256;
@@ -798,6 +813,7 @@ hipError_t enqueue_sort(const Plan& P, uint32_t head, const uint32_t* next_in, u
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }
+    mark(prof, s, kStagePack);
     switch (P.key_bytes) {
     case 1: e = Launcher<uint8_t>::pack(P, next_in, keys, ws, s); break;
     case 2: e = Launcher<uint16_t>::pack(P, next_in, keys, ws, s); break;
@@ -806,6 +822,7 @@ hipError_t enqueue_sort(const Plan& P, uint32_t head, const uint32_t* next_in, u
     }
     if (e != hipSuccess)
         return e;
+    mark(prof, s, kStageWalk0);
     switch (P.key_bytes) {
     case 1: e = Launcher<uint8_t>::walk0(P, head, ws, s); break;
     case 2: e = Launcher<uint16_t>::walk0(P, head, ws, s); break;
@@ -819,6 +836,7 @@ hipError_t enqueue_sort(const Plan& P, uint32_t head, const uint32_t* next_in, u
         const LevelPlan& L = P.lv[k];
         const LevelPlan& Lp = P.lv[k - 1];
         uint32_t blocks = (uint32_t)((L.n_static + 255) / 256);
+        mark(prof, s, kStageWalkUp);
         hipLaunchKernelGGL(k_walk_up, dim3(blocks), dim3(256), 0, s,
                            (const uint4*)(ws + Lp.o_rec_out), (uint32_t)Lp.n_static,
                            (uint32_t)Lp.dyn_cap, k - 1, (uint32_t)L.n_static,
@@ -829,6 +847,7 @@ hipError_t enqueue_sort(const Plan& P, uint32_t head, const uint32_t* next_in, u
     }
     {
         const LevelPlan& Lt = P.lv[P.levels - 1];
+        mark(prof, s, kStageBase);
         hipLaunchKernelGGL(k_base, dim3(1), dim3(kBaseThreads), 0, s,
                            (const uint4*)(ws + Lt.o_rec_out), (uint32_t)Lt.n_static,
                            (uint32_t)Lt.dyn_cap, P.levels - 1, (uint32_t)P.n,
@@ -840,6 +859,7 @@ hipError_t enqueue_sort(const Plan& P, uint32_t head, const uint32_t* next_in, u
         const LevelPlan& L = P.lv[k];       // chains of level k = elements of level k+1
         const LevelPlan& Lp = P.lv[k - 1];  // elements of level k
         uint32_t blocks = (uint32_t)((L.out_bound + 255) / 256);
+        mark(prof, s, kStageDown);
         hipLaunchKernelGGL(k_down, dim3(blocks), dim3(256), 0, s,
                            (const uint4*)(ws + L.o_rec_out), (const uint32_t*)(ws + L.o_offn_out),
                            (uint32_t)L.n_static, (uint32_t)L.dyn_cap, k,
@@ -848,6 +868,7 @@ hipError_t enqueue_sort(const Plan& P, uint32_t head, const uint32_t* next_in, u
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }
+    mark(prof, s, kStageUnchain);
     switch (P.key_bytes) {
     case 1: e = Launcher<uint8_t>::unchain(P, ws, s); break;
     case 2: e = Launcher<uint16_t>::unchain(P, ws, s); break;
@@ -857,21 +878,23 @@ hipError_t enqueue_sort(const Plan& P, uint32_t head, const uint32_t* next_in, u
     if (e != hipSuccess)
         return e;
     switch (P.key_bytes) {
-    case 1: e = Launcher<uint8_t>::passes(P, ws, s); break;
-    case 2: e = Launcher<uint16_t>::passes(P, ws, s); break;
-    case 4: e = Launcher<uint32_t>::passes(P, ws, s); break;
-    default: e = Launcher<uint64_t>::passes(P, ws, s); break;
+    case 1: e = Launcher<uint8_t>::passes(P, ws, s, prof); break;
+    case 2: e = Launcher<uint16_t>::passes(P, ws, s, prof); break;
+    case 4: e = Launcher<uint32_t>::passes(P, ws, s, prof); break;
+    default: e = Launcher<uint64_t>::passes(P, ws, s, prof); break;
     }
     if (e != hipSuccess)
         return e;
     {
         uint32_t blocks = (uint32_t)((P.n + 255) / 256);
+        mark(prof, s, kStageRelink);
         hipLaunchKernelGGL(k_relink, dim3(blocks), dim3(256), 0, s,
                            (const uint32_t*)(ws + P.o_idxA), (const uint32_t*)(ws + P.o_idxB),
                            (uint32_t)P.n, next_out, d_result, (const Header*)hdr);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }
+    mark(prof, s, kStageCount);
     return hipSuccess;
 }
 
