@@ -16,6 +16,7 @@ hipError_t enqueue_sort(const Plan& P, uint32_t head, const uint32_t* next_in, u
 hipError_t enqueue_empty(uint32_t* d_result, hipStream_t s);
 size_t entry_bytes(uint32_t key_bytes);
 size_t node_bytes(uint32_t key_bytes);
+size_t seg_len(uint32_t key_bytes);
 
 static size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
@@ -85,20 +86,20 @@ bool make_plan(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, Plan* P)
             return false;
         LevelPlan& L = P->lv[k];
         L.log_l = k == 0 ? kLog0 : kLogUp;
-        L.seg_cap = k == 0 ? kSeg0 : kSegUp;
-        L.m_bound = m;
+        L.m = m;
         L.n_static = 1 + ceil_div(m, 1ull << L.log_l);
-        L.dyn_cap = ceil_div(m, L.seg_cap) + 1;
-        L.out_bound = L.n_static + L.dyn_cap;
-        L.o_rec_out = off;
-        off = align_up(off + L.out_bound * 16);
-        L.o_members = off;
-        off = align_up(off + L.out_bound * L.seg_cap *
-                                 (k == 0 ? entry_bytes(P->key_bytes) : sizeof(uint32_t)));
-        L.o_offn_out = off;
-        off = align_up(off + L.out_bound * 4);
+        L.o_chain_rec = off;
+        off = align_up(off + L.n_static * 8);
+        if (k == 0) {
+            L.o_ent = off;
+            off = align_up(off + L.n_static * seg_len(P->key_bytes) * entry_bytes(P->key_bytes));
+            L.o_resume = off;
+            off = align_up(off + L.n_static * 4);
+        }
+        L.o_offn = off;
+        off = align_up(off + L.n_static * 4);
         k++;
-        m = L.out_bound;
+        m = L.n_static;
         if (m <= kBaseMax)
             break;
     }
@@ -189,7 +190,7 @@ extern "C" int pbit_sort_list_profiled(uint32_t head, const uint32_t* next_in,
 extern "C" const char* pbit_stage_name(int stage)
 {
     static const char* names[] = {"zero", "pack", "walk0", "walk_up", "base", "down",
-                                  "unchain", "schedule", "digit_pass", "relink", "end"};
+                                  "unchain", "schedule", "digit_pass", "relink", "walk2", "end"};
     if (stage < 0 || stage > (int)kStageCount)
         return "unknown";
     return names[stage];

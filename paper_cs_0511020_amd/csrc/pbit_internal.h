@@ -8,13 +8,10 @@ namespace pbit {
 constexpr uint32_t kNil = 0xFFFFFFFFu;
 
 // Level 0 walks the node list; every node index that is a multiple of
-// 2^kLog0 (and the head) starts a segment, and a segment holds at most kSeg0
-// nodes (a longer stretch continues in a freshly numbered segment).
+// 2^kLog0 (and the head) starts a chain.
 constexpr uint32_t kLog0 = 4;
-constexpr uint32_t kSeg0 = 16;
-// Levels >= 1 walk the list of segments of the level below.
+// Levels >= 1 walk the list of chains of the level below.
 constexpr uint32_t kLogUp = 3;
-constexpr uint32_t kSegUp = 32;
 // The last level is ranked inside one workgroup's LDS.
 constexpr uint32_t kBaseMax = 8192;
 constexpr int kMaxLevels = 12;
@@ -36,27 +33,27 @@ struct PassSched {
 struct Header {
     int32_t status;
     uint32_t final_buf;
-    uint32_t dyn[kMaxLevels];
+    uint32_t nil_count;       // next[] entries equal to NIL
+    uint32_t pad0;
+    uint64_t hsum[2];         // sum of h(next) over non-NIL next[] minus sum of h(i)
     uint32_t tile_ctr[kMaxPasses];
     PassSched sched[kMaxPasses];
 };
 
 struct LevelPlan {
-    uint32_t log_l;       // splitter spacing 2^log_l
-    uint32_t seg_cap;     // members per chain segment
-    uint64_t m_bound;     // element ids at this level are < m_bound
-    uint64_t n_static;    // chain 0 = head chain, chain 1 + j/L for splitter j
-    uint64_t dyn_cap;     // extra chains for stretches longer than seg_cap
-    uint64_t out_bound;   // n_static + dyn_cap = element ids of the level above
-    size_t o_rec_out;     // uint4 records of the level above (out_bound)
-    size_t o_members;     // chain members (out_bound * seg_cap entries)
-    size_t o_offn_out;    // node offsets of the level-above elements (u32)
+    uint32_t log_l;       // chain start spacing 2^log_l
+    uint64_t m;           // elements at this level
+    uint64_t n_static;    // chains (= elements of the next level)
+    size_t o_chain_rec;   // uint2 {successor chain, weight} per chain
+    size_t o_ent;         // level 0: stored head entries of every chain
+    size_t o_resume;      // level 0: node where the unstored rest of a chain starts
+    size_t o_offn;        // u32 offset (in nodes) of every chain
 };
 
 // Stages of one sort, in launch order (measurement hooks name them).
 enum Stage : int32_t {
     kStageZero = 0, kStagePack, kStageWalk0, kStageWalkUp, kStageBase, kStageDown,
-    kStageUnchain, kStageSchedule, kStagePass, kStageRelink, kStageCount
+    kStageUnchain, kStageSchedule, kStagePass, kStageRelink, kStageWalk2, kStageCount
 };
 
 // Optional event recording between stages: events[i] is recorded before the

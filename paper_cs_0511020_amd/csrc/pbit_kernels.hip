@@ -37,6 +37,9 @@ template <> struct __attribute__((aligned(16))) NodeRec<uint64_t> { uint32_t nex
 template <typename KeyT> struct Entry { uint32_t key; uint32_t idx; };
 template <> struct __attribute__((aligned(16))) Entry<uint64_t> { uint64_t key; uint32_t idx; uint32_t pad; };
 
+// Entries of a level-0 chain kept in registers by its walker.
+template <typename KeyT> struct SegLen { static constexpr uint32_t value = sizeof(KeyT) == 8 ? 16 : 32; };
+
 template <typename KeyT> __device__ __forceinline__ KeyT entry_key(const Entry<KeyT>& e) { return (KeyT)e.key; }
 
 __device__ __forceinline__ void set_error(int32_t* status, int32_t code)
@@ -63,6 +66,27 @@ __global__ void k_zero(uint32_t* __restrict__ p, size_t words)
         p[i] = 0u;
 }
 
+__device__ __forceinline__ uint64_t mix64(uint64_t x, uint64_t k)
+{
+    x ^= x >> 31;
+    x *= k;
+    x ^= x >> 29;
+    x *= 0xBF58476D1CE4E5B9ull;
+    x ^= x >> 32;
+    return x;
+}
+constexpr uint64_t kHashK1 = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kHashK2 = 0xD6E8FEB86659FD93ull;
+
+// Every walk kernel starts here: a list passes only if exactly one next[] is
+// NIL and the non-NIL next[] values are all nodes but the head, once each.
+__device__ __forceinline__ bool list_shape_ok(const Header* hdr, uint32_t head)
+{
+    return hdr->status == 0 && hdr->nil_count == 1 &&
+           hdr->hsum[0] + mix64(head + 1ull, kHashK1) == 0 &&
+           hdr->hsum[1] + mix64(head + 1ull, kHashK2) == 0;
+}
+
 // ---------------------------------------------------------------- pack
 // Node records and the count of every pattern value of every pass.
 template <typename KeyT, int RB>
@@ -79,206 +103,204 @@ __global__ __launch_bounds__(256) void k_pack(const uint32_t* __restrict__ next,
         s_hist[i] = 0;
     __syncthreads();
     bool bad = false;
+    uint64_t h1 = 0, h2 = 0;
+    uint32_t nils = 0;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += stride) {
-        uint32_t nx = next[i];
-        KeyT k = keys[i] ^ xor_mask;
+        const uint32_t nx = next[i];
+        const KeyT k = keys[i] ^ xor_mask;
         bad |= (nx != kNil) && (nx >= n);
+        if (nx == kNil) {
+            nils++;
+        } else {
+            h1 += mix64(nx + 1ull, kHashK1);
+            h2 += mix64(nx + 1ull, kHashK2);
+        }
+        h1 -= mix64(i + 1ull, kHashK1);
+        h2 -= mix64(i + 1ull, kHashK2);
         NodeRec<KeyT> r;
         r.next = nx;
         r.key = k;
         if constexpr (sizeof(KeyT) == 8) r.pad = 0;
         nodes[i] = r;
         for (uint32_t p = 0; p < passes; p++) {
-            uint32_t d = (uint32_t)(k >> (p * RB)) & (RADIX - 1u);
+            const uint32_t d = (uint32_t)(k >> (p * RB)) & (RADIX - 1u);
             atomicAdd(&s_hist[p * RADIX + d], 1u);
         }
     }
     if (bad)
         set_error(&hdr->status, PBIT_EMALFORMED);
+    // block sums of the in-degree hashes and the NIL count
+    for (int off = 32; off > 0; off >>= 1) {
+        h1 += (uint64_t)__shfl_xor((unsigned long long)h1, off, 64);
+        h2 += (uint64_t)__shfl_xor((unsigned long long)h2, off, 64);
+        nils += __shfl_xor(nils, off, 64);
+    }
+    __shared__ uint64_t s_h[2][4];
+    __shared__ uint32_t s_nil[4];
+    const uint32_t wave = threadIdx.x / 64;
+    if (__lane_id() == 0) {
+        s_h[0][wave] = h1;
+        s_h[1][wave] = h2;
+        s_nil[wave] = nils;
+    }
     __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t a = 0, b = 0;
+        uint32_t z = 0;
+        for (uint32_t w = 0; w < blockDim.x / 64; w++) {
+            a += s_h[0][w];
+            b += s_h[1][w];
+            z += s_nil[w];
+        }
+        atomicAdd((unsigned long long*)&hdr->hsum[0], (unsigned long long)a);
+        atomicAdd((unsigned long long*)&hdr->hsum[1], (unsigned long long)b);
+        if (z)
+            atomicAdd(&hdr->nil_count, z);
+    }
     for (uint32_t i = threadIdx.x; i < nbins; i += blockDim.x) {
-        uint32_t v = s_hist[i];
+        const uint32_t v = s_hist[i];
         if (v)
             atomicAdd(&hist[i], v);
     }
 }
 
-// ---------------------------------------------------------------- level-0 walk
-// Chain 0 starts at head, chain 1 + j/L at node j (j a multiple of L, j != head).
-// A chain runs until the next start node or NIL; every kSeg0 nodes it moves
-// on to a new segment numbered from n_static upwards.  Output per segment:
-// {successor segment, nodes, members, 0} and its (key, node) entries.
+// ---------------------------------------------------------------- list ranking
+// Sparse-ruler ranking (Helman & JaJa style).  At level k the elements
+// 0..m-1 form a list from `head` (element 0 for k >= 1).  Chain 0 starts at
+// the head, chain 1 + j/L at element j for every multiple j of L = 2^log_l
+// other than the head; a chain runs up to the next chain start or NIL.  One
+// thread walks one chain to its end: no atomics, and the hardware refills a
+// wave slot as soon as a wave's chains are done.  A chain's record is
+// {successor chain or NIL, weight}; the chains form the list of level k + 1.
+//
+// Level 0 keeps the first SegLen (key, node) entries of its chain in
+// registers and writes them to the chain's slot, with the node where the
+// rest of the chain resumes; after ranking, walk2 re-walks only those rests.
+// Levels >= 1 store nothing: their down pass walks the chain again.
+//
+// The walks assume every node has at most one predecessor; pack verifies it
+// (hash sums over next[]), so every node is walked once in total and a bad
+// list is rejected before any walk starts.
+
 template <typename KeyT>
-__global__ __launch_bounds__(256) void k_walk0(const NodeRec<KeyT>* __restrict__ nodes,
-                                               uint32_t n, uint32_t head, uint32_t n_static,
-                                               uint32_t dyn_cap, uint4* __restrict__ rec_out,
-                                               Entry<KeyT>* __restrict__ buf, Header* hdr)
+__global__ __launch_bounds__(256) void k_walk0(const NodeRec<KeyT>* __restrict__ nodes, uint32_t n,
+                                               uint32_t head, uint32_t n_static,
+                                               uint2* __restrict__ chain_rec,
+                                               Entry<KeyT>* __restrict__ ent,
+                                               uint32_t* __restrict__ resume, Header* hdr)
 {
+    constexpr uint32_t C = SegLen<KeyT>::value;
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_static)
         return;
-    const uint32_t lmask = (1u << kLog0) - 1u;
-    uint32_t start;
-    if (c == 0) {
-        start = head;
-    } else {
-        uint64_t s = (uint64_t)(c - 1) << kLog0;
+    if (!list_shape_ok(hdr, head)) {
+        if (c == 0 && hdr->status == 0)
+            set_error(&hdr->status, PBIT_EMALFORMED);
+        return;
+    }
+    uint32_t start = head;
+    if (c != 0) {
+        const uint64_t s = (uint64_t)(c - 1) << kLog0;
         if (s >= n || (uint32_t)s == head) {
-            rec_out[c] = make_uint4(kNil, 0, 0, 0);
+            chain_rec[c] = make_uint2(kNil, 0);
             return;
         }
         start = (uint32_t)s;
     }
-    uint32_t seg = c, cur = start;
-    for (;;) {
-        Entry<KeyT> e[kSeg0];
-        uint32_t len = 0, nx = kNil;
-        bool stop = false;
+    const uint32_t lmask = (1u << kLog0) - 1u;
+    Entry<KeyT> e[C];
+    uint32_t cur = start, len = 0, nx = kNil;
+    bool stop = false;
 #pragma unroll
-        for (uint32_t t = 0; t < kSeg0; t++) {
-            if (!stop) {
-                NodeRec<KeyT> r = nodes[cur];
-                e[t].key = r.key;
-                e[t].idx = cur;
-                len = t + 1;
-                nx = r.next;
-                if (nx == kNil) {
-                    stop = true;
-                } else if (nx >= n) {
-                    set_error(&hdr->status, PBIT_EMALFORMED);
-                    nx = kNil;
-                    stop = true;
-                } else if ((nx & lmask) == 0 || nx == head) {
-                    stop = true;
-                } else {
-                    cur = nx;
-                }
-            }
+    for (uint32_t t = 0; t < C; t++) {
+        if (!stop) {
+            const NodeRec<KeyT> r = nodes[cur];
+            e[t].key = r.key;
+            e[t].idx = cur;
+            if constexpr (sizeof(KeyT) == 8) e[t].pad = 0;
+            len = t + 1;
+            nx = r.next;
+            if (nx == kNil || nx >= n || (nx & lmask) == 0 || nx == head)
+                stop = true;
+            else
+                cur = nx;
         }
-        Entry<KeyT>* b = buf + (size_t)seg * kSeg0;
-#pragma unroll
-        for (uint32_t t = 0; t < kSeg0; t++)
-            if (t < len)
-                b[t] = e[t];
-        if (stop) {
-            uint32_t succ = (nx == kNil) ? kNil : (nx == head ? 0u : 1u + (nx >> kLog0));
-            rec_out[seg] = make_uint4(succ, len, len, 0);
-            return;
-        }
-        uint32_t d = atomicAdd(&hdr->dyn[0], 1u);
-        if (d >= dyn_cap) {
-            set_error(&hdr->status, PBIT_EMALFORMED);
-            rec_out[seg] = make_uint4(kNil, len, len, 0);
-            return;
-        }
-        const uint32_t nseg = n_static + d;
-        rec_out[seg] = make_uint4(nseg, len, len, 0);
-        seg = nseg;
-        cur = nx;
     }
+    const uint32_t rest_from = stop ? kNil : cur;
+    while (!stop) {
+        const NodeRec<KeyT> r = nodes[cur];
+        len++;
+        nx = r.next;
+        if (nx == kNil || nx >= n || (nx & lmask) == 0 || nx == head || len >= n)
+            stop = true;
+        else
+            cur = nx;
+    }
+    if (nx != kNil && nx >= n) {
+        set_error(&hdr->status, PBIT_EMALFORMED);
+        nx = kNil;
+    }
+    Entry<KeyT>* b = ent + (size_t)c * C;
+#pragma unroll
+    for (uint32_t t = 0; t < C; t++)
+        if (t < len)
+            b[t] = e[t];
+    resume[c] = rest_from;
+    const uint32_t succ = (nx == kNil) ? kNil : (nx == head ? 0u : 1u + (nx >> kLog0));
+    chain_rec[c] = make_uint2(succ, len);
 }
 
-// ---------------------------------------------------------------- upper walks
-// Same ruler over the element list of level k (records {succ, nodes, ...};
-// a record with 0 nodes is an unused id).  The head of every level >= 1 is
-// element 0.  m_k = prev_static + min(prev_dyn, prev_cap).
-__global__ __launch_bounds__(256) void k_walk_up(const uint4* __restrict__ rec_in,
-                                                 uint32_t prev_static, uint32_t prev_cap,
-                                                 int prev_level, uint32_t n_static,
-                                                 uint32_t dyn_cap, int level,
-                                                 uint4* __restrict__ rec_out,
-                                                 uint32_t* __restrict__ members, Header* hdr)
+// Level >= 1: chains over the records {successor, weight} of level k.
+__global__ __launch_bounds__(256) void k_walk_up(const uint2* __restrict__ recs, uint32_t m,
+                                                 uint32_t log_l, uint32_t n_static,
+                                                 uint2* __restrict__ chain_rec, Header* hdr)
 {
     if (hdr->status != 0)
         return;
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_static)
         return;
-    const uint32_t m = prev_static + min(hdr->dyn[prev_level], prev_cap);
-    const uint32_t lmask = (1u << kLogUp) - 1u;
-    uint32_t start;
-    if (c == 0) {
-        start = 0;
-    } else {
-        uint64_t s = (uint64_t)(c - 1) << kLogUp;
+    uint32_t start = 0;
+    if (c != 0) {
+        const uint64_t s = (uint64_t)(c - 1) << log_l;
         if (s >= m || s == 0) {
-            rec_out[c] = make_uint4(kNil, 0, 0, 0);
+            chain_rec[c] = make_uint2(kNil, 0);
             return;
         }
         start = (uint32_t)s;
     }
-    if (rec_in[start].y == 0) {  // unused id (empty chain of the level below)
-        if (c == 0)
-            set_error(&hdr->status, PBIT_EMALFORMED);
-        rec_out[c] = make_uint4(kNil, 0, 0, 0);
-        return;
-    }
-    uint32_t seg = c, cur = start;
+    const uint32_t lmask = (1u << log_l) - 1u;
+    uint32_t cur = start, w = 0, steps = 0, nx;
     for (;;) {
-        uint32_t mem[kSegUp];
-        uint32_t cnt = 0, nodes_sum = 0, nx = kNil;
-        bool stop = false;
-#pragma unroll
-        for (uint32_t t = 0; t < kSegUp; t++) {
-            if (!stop) {
-                uint4 r = rec_in[cur];
-                if (r.y == 0) {
-                    set_error(&hdr->status, PBIT_EMALFORMED);
-                    nx = kNil;
-                    stop = true;
-                } else {
-                    mem[t] = cur;
-                    cnt = t + 1;
-                    nodes_sum += r.y;
-                    nx = r.x;
-                    if (nx == kNil) {
-                        stop = true;
-                    } else if (nx >= m) {
-                        set_error(&hdr->status, PBIT_EMALFORMED);
-                        nx = kNil;
-                        stop = true;
-                    } else if ((nx & lmask) == 0) {
-                        stop = true;
-                    } else {
-                        cur = nx;
-                    }
-                }
-            }
-        }
-        uint32_t* b = members + (size_t)seg * kSegUp;
-#pragma unroll
-        for (uint32_t t = 0; t < kSegUp; t++)
-            if (t < cnt)
-                b[t] = mem[t];
-        if (stop) {
-            uint32_t succ = (nx == kNil) ? kNil : (nx == 0 ? 0u : 1u + (nx >> kLogUp));
-            rec_out[seg] = make_uint4(succ, nodes_sum, cnt, 0);
-            return;
-        }
-        uint32_t d = atomicAdd(&hdr->dyn[level], 1u);
-        if (d >= dyn_cap) {
+        const uint2 r = recs[cur];
+        if (r.y == 0) {  // empty chain of the level below: not part of a list
             set_error(&hdr->status, PBIT_EMALFORMED);
-            rec_out[seg] = make_uint4(kNil, nodes_sum, cnt, 0);
-            return;
+            nx = kNil;
+            break;
         }
-        const uint32_t nseg = n_static + d;
-        rec_out[seg] = make_uint4(nseg, nodes_sum, cnt, 0);
-        seg = nseg;
+        w += r.y;
+        nx = r.x;
+        if (nx == kNil || nx >= m || (nx & lmask) == 0 || ++steps >= m)
+            break;
         cur = nx;
     }
+    if (nx != kNil && (nx >= m || steps >= m)) {
+        set_error(&hdr->status, PBIT_EMALFORMED);
+        nx = kNil;
+    }
+    chain_rec[c] = make_uint2(nx == kNil ? kNil : (nx == 0 ? 0u : 1u + (nx >> log_l)), w);
 }
 
 // ---------------------------------------------------------------- base
-// Pointer jumping (Wyllie) in LDS: suffix node counts from every element to
-// the end of the list, then offset = total - suffix.  The list must end in
-// NIL from element 0 and cover exactly n nodes.
+// Pointer jumping (Wyllie) in LDS: suffix weights from every element to the
+// end of the list, then offset = total - suffix.  The list must end in NIL
+// from element 0 and cover exactly n nodes.
 constexpr int kBaseThreads = 1024;
 constexpr int kBasePer = kBaseMax / kBaseThreads;
 
-__global__ __launch_bounds__(kBaseThreads) void k_base(const uint4* __restrict__ rec,
-                                                       uint32_t prev_static, uint32_t prev_cap,
-                                                       int prev_level, uint32_t n_total,
+__global__ __launch_bounds__(kBaseThreads) void k_base(const uint2* __restrict__ rec, uint32_t m,
+                                                       uint32_t n_total,
                                                        uint32_t* __restrict__ offn, Header* hdr)
 {
     __shared__ uint32_t s_ptr[kBaseMax];
@@ -286,20 +308,18 @@ __global__ __launch_bounds__(kBaseThreads) void k_base(const uint4* __restrict__
     __shared__ int s_bad;
     if (hdr->status != 0)
         return;
-    const uint32_t m = min(prev_static + min(hdr->dyn[prev_level], prev_cap), kBaseMax);
+    m = min(m, kBaseMax);
     const int tid = threadIdx.x;
     if (tid == 0)
         s_bad = 0;
     for (int j = 0; j < kBasePer; j++) {
-        uint32_t i = tid + j * kBaseThreads;
+        const uint32_t i = tid + j * kBaseThreads;
         uint32_t p = kNil, v = 0;
         if (i < m) {
-            uint4 r = rec[i];
+            const uint2 r = rec[i];
             if (r.y != 0) {
-                p = r.x;
+                p = (r.x != kNil && r.x >= m) ? kNil : r.x;  // caught below: total != n
                 v = r.y;
-                if (p != kNil && p >= m)
-                    p = kNil;  // caught below: the total cannot reach n
             }
         }
         s_ptr[i] = p;
@@ -313,7 +333,7 @@ __global__ __launch_bounds__(kBaseThreads) void k_base(const uint4* __restrict__
         uint32_t np[kBasePer], nv[kBasePer];
 #pragma unroll
         for (int j = 0; j < kBasePer; j++) {
-            uint32_t i = tid + j * kBaseThreads;
+            const uint32_t i = tid + j * kBaseThreads;
             uint32_t p = s_ptr[i];
             uint32_t v = s_val[i];
             if (p != kNil) {
@@ -326,7 +346,7 @@ __global__ __launch_bounds__(kBaseThreads) void k_base(const uint4* __restrict__
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < kBasePer; j++) {
-            uint32_t i = tid + j * kBaseThreads;
+            const uint32_t i = tid + j * kBaseThreads;
             s_ptr[i] = np[j];
             s_val[i] = nv[j];
         }
@@ -341,66 +361,101 @@ __global__ __launch_bounds__(kBaseThreads) void k_base(const uint4* __restrict__
     if (s_bad)
         return;
     for (int j = 0; j < kBasePer; j++) {
-        uint32_t i = tid + j * kBaseThreads;
+        const uint32_t i = tid + j * kBaseThreads;
         if (i < m)
             offn[i] = total - s_val[i];
     }
 }
 
 // ---------------------------------------------------------------- down
-// Offsets of the members of each chain of level k from the chain's offset.
-__global__ __launch_bounds__(256) void k_down(const uint4* __restrict__ rec_chain,
+// Level k >= 1: walk each chain again, giving each element its offset
+// (chain offset plus the weights before it).
+__global__ __launch_bounds__(256) void k_down(const uint2* __restrict__ recs, uint32_t m,
+                                              uint32_t log_l, uint32_t n_static,
+                                              const uint2* __restrict__ chain_rec,
                                               const uint32_t* __restrict__ offn_chain,
-                                              uint32_t chain_static, uint32_t chain_cap,
-                                              int level, const uint32_t* __restrict__ members,
-                                              const uint4* __restrict__ rec_elem,
                                               uint32_t* __restrict__ offn_elem, Header* hdr)
 {
     if (hdr->status != 0)
         return;
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t m = chain_static + min(hdr->dyn[level], chain_cap);
-    if (c >= m)
+    if (c >= n_static)
         return;
-    const uint4 r = rec_chain[c];
-    if (r.y == 0)
+    const uint2 cr = chain_rec[c];
+    if (cr.y == 0)
         return;
-    uint32_t off = offn_chain[c];
-    const uint32_t* mem = members + (size_t)c * kSegUp;
-    const uint32_t cnt = min(r.z, kSegUp);
-    for (uint32_t t = 0; t < cnt; t++) {
-        uint32_t j = mem[t];
-        offn_elem[j] = off;
-        off += rec_elem[j].y;
+    const uint32_t start = c == 0 ? 0u : (c - 1) << log_l;
+    const uint32_t lmask = (1u << log_l) - 1u;
+    uint32_t cur = start, off = offn_chain[c];
+    for (uint32_t steps = 0; steps < m; steps++) {
+        const uint2 r = recs[cur];
+        offn_elem[cur] = off;
+        off += r.y;
+        const uint32_t nx = r.x;
+        if (nx == kNil || nx >= m || (nx & lmask) == 0)
+            break;
+        cur = nx;
     }
 }
 
 // ---------------------------------------------------------------- unchain
-// Level-0 segments to list order: keys and node indices at their offsets.
+// The stored head of every level-0 chain to list order.
 template <typename KeyT>
-__global__ __launch_bounds__(256) void k_unchain(const uint4* __restrict__ rec_seg,
-                                                 const uint32_t* __restrict__ offn_seg,
-                                                 uint32_t seg_static, uint32_t seg_cap,
-                                                 const Entry<KeyT>* __restrict__ buf, uint32_t n,
+__global__ __launch_bounds__(256) void k_unchain(const uint2* __restrict__ chain_rec,
+                                                 const Entry<KeyT>* __restrict__ ent,
+                                                 uint32_t n_static,
+                                                 const uint32_t* __restrict__ offn_chain, uint32_t n,
                                                  KeyT* __restrict__ keys_l,
                                                  uint32_t* __restrict__ idx_l, Header* hdr)
 {
+    constexpr uint32_t C = SegLen<KeyT>::value;
     if (hdr->status != 0)
         return;
     const uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-    const uint32_t s = (uint32_t)(g / kSeg0), t = (uint32_t)(g % kSeg0);
-    const uint32_t m = seg_static + min(hdr->dyn[0], seg_cap);
-    if (s >= m)
+    const uint32_t c = (uint32_t)(g / C), t = (uint32_t)(g % C);
+    if (c >= n_static)
         return;
-    const uint4 r = rec_seg[s];
-    if (t >= r.y)
+    const uint32_t len = chain_rec[c].y;
+    if (t >= len)
         return;
-    const uint32_t pos = offn_seg[s] + t;
+    const uint32_t pos = offn_chain[c] + t;
     if (pos >= n)
         return;
-    const Entry<KeyT> e = buf[(size_t)s * kSeg0 + t];
+    const Entry<KeyT> e = ent[(size_t)c * C + t];
     keys_l[pos] = entry_key<KeyT>(e);
     idx_l[pos] = e.idx;
+}
+
+// The rest of every level-0 chain longer than the stored head, walked again
+// from its resume node and written straight to list order.
+template <typename KeyT>
+__global__ __launch_bounds__(256) void k_walk2(const NodeRec<KeyT>* __restrict__ nodes,
+                                               const uint2* __restrict__ chain_rec,
+                                               const uint32_t* __restrict__ resume,
+                                               uint32_t n_static,
+                                               const uint32_t* __restrict__ offn_chain, uint32_t n,
+                                               KeyT* __restrict__ keys_l,
+                                               uint32_t* __restrict__ idx_l, Header* hdr)
+{
+    constexpr uint32_t C = SegLen<KeyT>::value;
+    if (hdr->status != 0)
+        return;
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_static)
+        return;
+    const uint32_t len = chain_rec[c].y;
+    if (len <= C)
+        return;
+    uint32_t cur = resume[c];
+    uint32_t pos = offn_chain[c] + C;
+    const uint32_t end = min(offn_chain[c] + len, n);
+    while (pos < end && cur < n) {
+        const NodeRec<KeyT> r = nodes[cur];
+        keys_l[pos] = (KeyT)r.key;
+        idx_l[pos] = cur;
+        pos++;
+        cur = r.next;
+    }
 }
 
 // ---------------------------------------------------------------- schedule
@@ -681,7 +736,7 @@ struct Launcher {
     static hipError_t pack(const Plan& P, const uint32_t* next, const void* keys, char* ws,
                            hipStream_t s);
     static hipError_t walk0(const Plan& P, uint32_t head, char* ws, hipStream_t s);
-    static hipError_t unchain(const Plan& P, char* ws, hipStream_t s);
+    static hipError_t unchain(const Plan& P, char* ws, hipStream_t s, Prof* prof);
     static hipError_t passes(const Plan& P, char* ws, hipStream_t s, Prof* prof);
 };
 
@@ -762,31 +817,41 @@ template <typename KeyT>
 hipError_t Launcher<KeyT>::walk0(const Plan& P, uint32_t head, char* ws, hipStream_t s)
 {
     const LevelPlan& L = P.lv[0];
-    uint32_t blocks = (uint32_t)((L.n_static + 255) / 256);
-    hipLaunchKernelGGL((k_walk0<KeyT>), dim3(blocks), dim3(256), 0, s,
-                       (const NodeRec<KeyT>*)(ws + P.o_nodes), (uint32_t)P.n, head,
-                       (uint32_t)L.n_static, (uint32_t)L.dyn_cap, (uint4*)(ws + L.o_rec_out),
-                       (Entry<KeyT>*)(ws + L.o_members), (Header*)(ws + P.o_header));
+    hipLaunchKernelGGL((k_walk0<KeyT>), dim3((uint32_t)((L.n_static + 255) / 256)), dim3(256), 0,
+                       s, (const NodeRec<KeyT>*)(ws + P.o_nodes), (uint32_t)P.n, head,
+                       (uint32_t)L.n_static, (uint2*)(ws + L.o_chain_rec),
+                       (Entry<KeyT>*)(ws + L.o_ent), (uint32_t*)(ws + L.o_resume),
+                       (Header*)(ws + P.o_header));
     return hipGetLastError();
 }
 
 template <typename KeyT>
-hipError_t Launcher<KeyT>::unchain(const Plan& P, char* ws, hipStream_t s)
+hipError_t Launcher<KeyT>::unchain(const Plan& P, char* ws, hipStream_t s, Prof* prof)
 {
+    constexpr uint32_t C = SegLen<KeyT>::value;
     const LevelPlan& L = P.lv[0];
-    uint64_t threads = L.out_bound * kSeg0;
-    uint32_t blocks = (uint32_t)((threads + 255) / 256);
-    hipLaunchKernelGGL((k_unchain<KeyT>), dim3(blocks), dim3(256), 0, s,
-                       (const uint4*)(ws + L.o_rec_out), (const uint32_t*)(ws + L.o_offn_out),
-                       (uint32_t)L.n_static, (uint32_t)L.dyn_cap,
-                       (const Entry<KeyT>*)(ws + L.o_members), (uint32_t)P.n,
+    const uint64_t threads = L.n_static * C;
+    mark(prof, s, kStageUnchain);
+    hipLaunchKernelGGL((k_unchain<KeyT>), dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s,
+                       (const uint2*)(ws + L.o_chain_rec), (const Entry<KeyT>*)(ws + L.o_ent),
+                       (uint32_t)L.n_static, (const uint32_t*)(ws + L.o_offn), (uint32_t)P.n,
                        (KeyT*)(ws + P.o_keysA), (uint32_t*)(ws + P.o_idxA),
                        (Header*)(ws + P.o_header));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    mark(prof, s, kStageWalk2);
+    hipLaunchKernelGGL((k_walk2<KeyT>), dim3((uint32_t)((L.n_static + 255) / 256)), dim3(256), 0, s,
+                       (const NodeRec<KeyT>*)(ws + P.o_nodes), (const uint2*)(ws + L.o_chain_rec),
+                       (const uint32_t*)(ws + L.o_resume), (uint32_t)L.n_static,
+                       (const uint32_t*)(ws + L.o_offn), (uint32_t)P.n, (KeyT*)(ws + P.o_keysA),
+                       (uint32_t*)(ws + P.o_idxA), (Header*)(ws + P.o_header));
     return hipGetLastError();
 }
 
 size_t entry_bytes(uint32_t key_bytes) { return key_bytes == 8 ? 16 : 8; }
 size_t node_bytes(uint32_t key_bytes) { return key_bytes == 8 ? 16 : 8; }
+size_t seg_len(uint32_t key_bytes) { return key_bytes == 8 ? 16 : 32; }
 
 static inline void mark(Prof* prof, hipStream_t s, int32_t stage)
 {
@@ -835,13 +900,10 @@ hipError_t enqueue_sort(const Plan& P, uint32_t head, const uint32_t* next_in, u
     for (int k = 1; k < P.levels; k++) {
         const LevelPlan& L = P.lv[k];
         const LevelPlan& Lp = P.lv[k - 1];
-        uint32_t blocks = (uint32_t)((L.n_static + 255) / 256);
         mark(prof, s, kStageWalkUp);
-        hipLaunchKernelGGL(k_walk_up, dim3(blocks), dim3(256), 0, s,
-                           (const uint4*)(ws + Lp.o_rec_out), (uint32_t)Lp.n_static,
-                           (uint32_t)Lp.dyn_cap, k - 1, (uint32_t)L.n_static,
-                           (uint32_t)L.dyn_cap, k, (uint4*)(ws + L.o_rec_out),
-                           (uint32_t*)(ws + L.o_members), hdr);
+        hipLaunchKernelGGL(k_walk_up, dim3((uint32_t)((L.n_static + 255) / 256)), dim3(256), 0, s,
+                           (const uint2*)(ws + Lp.o_chain_rec), (uint32_t)L.m, L.log_l,
+                           (uint32_t)L.n_static, (uint2*)(ws + L.o_chain_rec), hdr);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }
@@ -849,31 +911,27 @@ hipError_t enqueue_sort(const Plan& P, uint32_t head, const uint32_t* next_in, u
         const LevelPlan& Lt = P.lv[P.levels - 1];
         mark(prof, s, kStageBase);
         hipLaunchKernelGGL(k_base, dim3(1), dim3(kBaseThreads), 0, s,
-                           (const uint4*)(ws + Lt.o_rec_out), (uint32_t)Lt.n_static,
-                           (uint32_t)Lt.dyn_cap, P.levels - 1, (uint32_t)P.n,
-                           (uint32_t*)(ws + Lt.o_offn_out), hdr);
+                           (const uint2*)(ws + Lt.o_chain_rec), (uint32_t)Lt.n_static,
+                           (uint32_t)P.n, (uint32_t*)(ws + Lt.o_offn), hdr);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }
     for (int k = P.levels - 1; k >= 1; k--) {
-        const LevelPlan& L = P.lv[k];       // chains of level k = elements of level k+1
-        const LevelPlan& Lp = P.lv[k - 1];  // elements of level k
-        uint32_t blocks = (uint32_t)((L.out_bound + 255) / 256);
+        const LevelPlan& L = P.lv[k];
+        const LevelPlan& Lp = P.lv[k - 1];
         mark(prof, s, kStageDown);
-        hipLaunchKernelGGL(k_down, dim3(blocks), dim3(256), 0, s,
-                           (const uint4*)(ws + L.o_rec_out), (const uint32_t*)(ws + L.o_offn_out),
-                           (uint32_t)L.n_static, (uint32_t)L.dyn_cap, k,
-                           (const uint32_t*)(ws + L.o_members), (const uint4*)(ws + Lp.o_rec_out),
-                           (uint32_t*)(ws + Lp.o_offn_out), hdr);
+        hipLaunchKernelGGL(k_down, dim3((uint32_t)((L.n_static + 255) / 256)), dim3(256), 0, s,
+                           (const uint2*)(ws + Lp.o_chain_rec), (uint32_t)L.m, L.log_l,
+                           (uint32_t)L.n_static, (const uint2*)(ws + L.o_chain_rec),
+                           (const uint32_t*)(ws + L.o_offn), (uint32_t*)(ws + Lp.o_offn), hdr);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }
-    mark(prof, s, kStageUnchain);
     switch (P.key_bytes) {
-    case 1: e = Launcher<uint8_t>::unchain(P, ws, s); break;
-    case 2: e = Launcher<uint16_t>::unchain(P, ws, s); break;
-    case 4: e = Launcher<uint32_t>::unchain(P, ws, s); break;
-    default: e = Launcher<uint64_t>::unchain(P, ws, s); break;
+    case 1: e = Launcher<uint8_t>::unchain(P, ws, s, prof); break;
+    case 2: e = Launcher<uint16_t>::unchain(P, ws, s, prof); break;
+    case 4: e = Launcher<uint32_t>::unchain(P, ws, s, prof); break;
+    default: e = Launcher<uint64_t>::unchain(P, ws, s, prof); break;
     }
     if (e != hipSuccess)
         return e;

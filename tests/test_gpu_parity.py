@@ -143,6 +143,10 @@ def test_malformed_lists_are_rejected_untouched():
     bad = nxt.copy(); bad[order[100]] = n + 5; cases["index out of range"] = bad
     bad = nxt.copy(); bad[order[n - 10]] = NIL; cases["short list"] = bad
     bad = nxt.copy(); bad[order[-1]] = order[0]; cases["cycle through head"] = bad
+    # every node keeps one predecessor: a shorter path from head plus a
+    # separate cycle (caught by the length check, not the in-degree check)
+    bad = nxt.copy(); bad[order[n // 2 - 1]] = NIL; bad[order[-1]] = order[n // 2]
+    cases["path plus disjoint cycle"] = bad
     for name, b in cases.items():
         say("malformed:", name)
         h, st, got = gpu_sort(head, b, keys, 8)
