@@ -16,7 +16,7 @@ hipError_t enqueue_sort(const Plan& P, uint32_t head, const uint32_t* next_in, u
 hipError_t enqueue_empty(uint32_t* d_result, hipStream_t s);
 size_t entry_bytes(uint32_t key_bytes);
 size_t node_bytes(uint32_t key_bytes);
-size_t seg_len(uint32_t key_bytes);
+size_t chain_cap();
 
 static size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
@@ -92,7 +92,7 @@ bool make_plan(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, Plan* P)
         off = align_up(off + L.n_static * 8);
         if (k == 0) {
             L.o_ent = off;
-            off = align_up(off + L.n_static * seg_len(P->key_bytes) * entry_bytes(P->key_bytes));
+            off = align_up(off + L.n_static * chain_cap() * entry_bytes(P->key_bytes));
             L.o_resume = off;
             off = align_up(off + L.n_static * 4);
         }

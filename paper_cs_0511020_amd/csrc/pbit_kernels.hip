@@ -39,6 +39,8 @@ template <> struct __attribute__((aligned(16))) Entry<uint64_t> { uint64_t key; 
 
 // Entries of a level-0 chain kept in registers by its walker.
 template <typename KeyT> struct SegLen { static constexpr uint32_t value = sizeof(KeyT) == 8 ? 16 : 32; };
+// Entries stored per level-0 chain slot; nodes past this are re-walked.
+constexpr uint32_t kChainCap = 128;
 
 template <typename KeyT> __device__ __forceinline__ KeyT entry_key(const Entry<KeyT>& e) { return (KeyT)e.key; }
 
@@ -175,8 +177,9 @@ __global__ __launch_bounds__(256) void k_pack(const uint32_t* __restrict__ next,
 // {successor chain or NIL, weight}; the chains form the list of level k + 1.
 //
 // Level 0 keeps the first SegLen (key, node) entries of its chain in
-// registers and writes them to the chain's slot, with the node where the
-// rest of the chain resumes; after ranking, walk2 re-walks only those rests.
+// registers, stores the following ones straight to the chain's slot of
+// kChainCap entries, and records the node where a longer chain resumes; after
+// ranking, walk2 re-walks only those (rare) rests.
 // Levels >= 1 store nothing: their down pass walks the chain again.
 //
 // The walks assume every node has at most one predecessor; pack verifies it
@@ -227,9 +230,19 @@ __global__ __launch_bounds__(256) void k_walk0(const NodeRec<KeyT>* __restrict__
                 cur = nx;
         }
     }
-    const uint32_t rest_from = stop ? kNil : cur;
+    Entry<KeyT>* b = ent + (size_t)c * kChainCap;
+    uint32_t rest_from = kNil;
     while (!stop) {
         const NodeRec<KeyT> r = nodes[cur];
+        if (len < kChainCap) {
+            Entry<KeyT> x;
+            x.key = r.key;
+            x.idx = cur;
+            if constexpr (sizeof(KeyT) == 8) x.pad = 0;
+            b[len] = x;
+        } else if (len == kChainCap) {
+            rest_from = cur;
+        }
         len++;
         nx = r.next;
         if (nx == kNil || nx >= n || (nx & lmask) == 0 || nx == head || len >= n)
@@ -241,7 +254,6 @@ __global__ __launch_bounds__(256) void k_walk0(const NodeRec<KeyT>* __restrict__
         set_error(&hdr->status, PBIT_EMALFORMED);
         nx = kNil;
     }
-    Entry<KeyT>* b = ent + (size_t)c * C;
 #pragma unroll
     for (uint32_t t = 0; t < C; t++)
         if (t < len)
@@ -408,26 +420,28 @@ __global__ __launch_bounds__(256) void k_unchain(const uint2* __restrict__ chain
                                                  KeyT* __restrict__ keys_l,
                                                  uint32_t* __restrict__ idx_l, Header* hdr)
 {
-    constexpr uint32_t C = SegLen<KeyT>::value;
+    constexpr uint32_t G = 16;  // threads per chain
     if (hdr->status != 0)
         return;
     const uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-    const uint32_t c = (uint32_t)(g / C), t = (uint32_t)(g % C);
+    const uint32_t c = (uint32_t)(g / G);
     if (c >= n_static)
         return;
-    const uint32_t len = chain_rec[c].y;
-    if (t >= len)
-        return;
-    const uint32_t pos = offn_chain[c] + t;
-    if (pos >= n)
-        return;
-    const Entry<KeyT> e = ent[(size_t)c * C + t];
-    keys_l[pos] = entry_key<KeyT>(e);
-    idx_l[pos] = e.idx;
+    const uint32_t len = min(chain_rec[c].y, kChainCap);
+    const uint32_t base = offn_chain[c];
+    const Entry<KeyT>* b = ent + (size_t)c * kChainCap;
+    for (uint32_t t = (uint32_t)(g % G); t < len; t += G) {
+        const uint32_t pos = base + t;
+        if (pos >= n)
+            break;
+        const Entry<KeyT> e = b[t];
+        keys_l[pos] = entry_key<KeyT>(e);
+        idx_l[pos] = e.idx;
+    }
 }
 
-// The rest of every level-0 chain longer than the stored head, walked again
-// from its resume node and written straight to list order.
+// The rest of every level-0 chain longer than its slot, walked again from
+// its resume node and written straight to list order.
 template <typename KeyT>
 __global__ __launch_bounds__(256) void k_walk2(const NodeRec<KeyT>* __restrict__ nodes,
                                                const uint2* __restrict__ chain_rec,
@@ -437,17 +451,16 @@ __global__ __launch_bounds__(256) void k_walk2(const NodeRec<KeyT>* __restrict__
                                                KeyT* __restrict__ keys_l,
                                                uint32_t* __restrict__ idx_l, Header* hdr)
 {
-    constexpr uint32_t C = SegLen<KeyT>::value;
     if (hdr->status != 0)
         return;
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_static)
         return;
     const uint32_t len = chain_rec[c].y;
-    if (len <= C)
+    if (len <= kChainCap)
         return;
     uint32_t cur = resume[c];
-    uint32_t pos = offn_chain[c] + C;
+    uint32_t pos = offn_chain[c] + kChainCap;
     const uint32_t end = min(offn_chain[c] + len, n);
     while (pos < end && cur < n) {
         const NodeRec<KeyT> r = nodes[cur];
@@ -828,9 +841,8 @@ hipError_t Launcher<KeyT>::walk0(const Plan& P, uint32_t head, char* ws, hipStre
 template <typename KeyT>
 hipError_t Launcher<KeyT>::unchain(const Plan& P, char* ws, hipStream_t s, Prof* prof)
 {
-    constexpr uint32_t C = SegLen<KeyT>::value;
     const LevelPlan& L = P.lv[0];
-    const uint64_t threads = L.n_static * C;
+    const uint64_t threads = L.n_static * 16;
     mark(prof, s, kStageUnchain);
     hipLaunchKernelGGL((k_unchain<KeyT>), dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s,
                        (const uint2*)(ws + L.o_chain_rec), (const Entry<KeyT>*)(ws + L.o_ent),
@@ -851,7 +863,7 @@ hipError_t Launcher<KeyT>::unchain(const Plan& P, char* ws, hipStream_t s, Prof*
 
 size_t entry_bytes(uint32_t key_bytes) { return key_bytes == 8 ? 16 : 8; }
 size_t node_bytes(uint32_t key_bytes) { return key_bytes == 8 ? 16 : 8; }
-size_t seg_len(uint32_t key_bytes) { return key_bytes == 8 ? 16 : 32; }
+size_t chain_cap() { return kChainCap; }
 
 static inline void mark(Prof* prof, hipStream_t s, int32_t stage)
 {
