@@ -17,6 +17,7 @@ hipError_t enqueue_empty(uint32_t* d_result, hipStream_t s);
 size_t entry_bytes(uint32_t key_bytes);
 size_t node_bytes(uint32_t key_bytes);
 size_t chain_cap();
+uint32_t pass_tile(uint32_t key_bytes);
 
 static size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
@@ -51,8 +52,8 @@ bool make_plan(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, Plan* P)
     P->passes = M / P->K;
     P->flags = flags;
     P->key_bytes = M / 8;
-    P->items = P->key_bytes == 8 ? 8 : 16;
-    P->tile = 256 * P->items;
+    P->tile = pass_tile(P->key_bytes);
+    P->items = P->tile / 512;
     P->tiles = (uint32_t)ceil_div(n ? n : 1, P->tile);
     if (n == 0) {
         P->total = 256;

@@ -36,7 +36,6 @@ struct Header {
     uint32_t nil_count;       // next[] entries equal to NIL
     uint32_t pad0;
     uint64_t hsum[2];         // sum of h(next) over non-NIL next[] minus sum of h(i)
-    uint32_t tile_ctr[kMaxPasses];
     PassSched sched[kMaxPasses];
 };
 

@@ -37,6 +37,11 @@ template <> struct __attribute__((aligned(16))) NodeRec<uint64_t> { uint32_t nex
 template <typename KeyT> struct Entry { uint32_t key; uint32_t idx; };
 template <> struct __attribute__((aligned(16))) Entry<uint64_t> { uint64_t key; uint32_t idx; uint32_t pad; };
 
+// Digit-pass tile: kPassBlock threads x PassItems items.
+constexpr int kPassBlock = 512;
+template <typename KeyT> struct PassItems { static constexpr int value = sizeof(KeyT) == 8 ? 8 : 16; };
+uint32_t pass_tile(uint32_t key_bytes) { return kPassBlock * (key_bytes == 8 ? 8 : 16); }
+
 // Entries of a level-0 chain kept in registers by its walker.
 template <typename KeyT> struct SegLen { static constexpr uint32_t value = sizeof(KeyT) == 8 ? 16 : 32; };
 // Entries stored per level-0 chain slot; nodes past this are re-walked.
@@ -528,19 +533,28 @@ __global__ __launch_bounds__(256) void k_schedule(const uint32_t* __restrict__ h
 }
 
 // ---------------------------------------------------------------- digit pass
-// One stable split on the pattern at bit `shift`: a tile of BLOCK*ITEMS
-// consecutive list positions is ranked in registers and LDS, its per-digit
-// counts are chained across tiles with decoupled look-back (tiles take
-// tickets in order so every tile waits only on tiles already running), and
-// the tile is written out grouped by digit.
+// One stable split on the pattern at bit `shift`.  A tile of BLOCK * ITEMS
+// consecutive list positions (tile = block index) is loaded wave-striped,
+// ranked per wave (K ballots give each item the mask of lanes with the same
+// digit; the first lane of each group adds the group size to a wave-private
+// LDS counter with one in-order LDS atomic, and peers take the returned base
+// from it), scanned across waves, chained across tiles by decoupled look-back
+// (Merrill & Garland), staged in LDS grouped by digit and written out in
+// runs.  The look-back spin is bounded: a tile that waits too long on a
+// predecessor counts that predecessor's digit in its input itself, so no
+// tile ever waits on a tile that has not been scheduled.
+template <typename KeyT> struct KV { KeyT key; uint32_t idx; };
+
 __device__ __forceinline__ uint64_t lanemask_lt()
 {
     const uint32_t lane = __lane_id();
     return (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 }
 
+constexpr uint32_t kSpinLimit = 4096;
+
 template <typename KeyT, int RB, int BLOCK, int ITEMS>
-__global__ __launch_bounds__(BLOCK) void k_digit_pass(uint32_t pass, uint32_t shift, uint32_t n,
+__global__ __launch_bounds__(BLOCK, 4) void k_digit_pass(uint32_t pass, uint32_t shift, uint32_t n,
                                                       KeyT* __restrict__ keysA,
                                                       uint32_t* __restrict__ idxA,
                                                       KeyT* __restrict__ keysB,
@@ -554,10 +568,8 @@ __global__ __launch_bounds__(BLOCK) void k_digit_pass(uint32_t pass, uint32_t sh
     __shared__ uint32_t s_wave[WAVES][RADIX];
     __shared__ uint32_t s_count[RADIX];
     __shared__ uint32_t s_start[RADIX];
-    __shared__ uint32_t s_gbase[RADIX];
-    __shared__ KeyT s_keys[TILE];
-    __shared__ uint32_t s_idx[TILE];
-    __shared__ uint32_t s_tile;
+    __shared__ int32_t s_delta[RADIX];
+    __shared__ KV<KeyT> s_kv[TILE];
 
     if (hdr->status != 0)
         return;
@@ -573,17 +585,13 @@ __global__ __launch_bounds__(BLOCK) void k_digit_pass(uint32_t pass, uint32_t sh
     const uint32_t wave = tid / 64, lane = tid % 64;
     for (uint32_t i = tid; i < WAVES * RADIX; i += BLOCK)
         (&s_wave[0][0])[i] = 0;
-    if (tid == 0)
-        s_tile = atomicAdd(&hdr->tile_ctr[pass], 1u);
     __syncthreads();
-    const uint32_t tile = s_tile;
+    const uint32_t tile = blockIdx.x;
     const uint64_t tbase = (uint64_t)tile * TILE;
     const uint64_t wbase = tbase + (uint64_t)wave * (64 * ITEMS);
 
     KeyT key[ITEMS];
-    uint32_t idx[ITEMS];
-    uint32_t dig[ITEMS];
-    uint32_t rank[ITEMS];
+    uint32_t idx[ITEMS], dig[ITEMS], rank[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
         const uint64_t e = wbase + (uint64_t)i * 64 + lane;
@@ -597,6 +605,8 @@ __global__ __launch_bounds__(BLOCK) void k_digit_pass(uint32_t pass, uint32_t sh
             dig[i] = RADIX;
         }
     }
+    // dig[i] bits: 0..8 digit (RADIX = invalid), 16..21 rank in the wave's
+    // group, 24..29 the group's first lane (which holds the LDS base)
     const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
@@ -608,14 +618,18 @@ __global__ __launch_bounds__(BLOCK) void k_digit_pass(uint32_t pass, uint32_t sh
             const uint64_t bb = __ballot(bit);
             peers &= bit ? bb : ~bb;
         }
-        if (valid) {
-            const uint32_t below = __popcll(peers & lt);
-            const uint32_t base = s_wave[wave][dig[i]];
-            rank[i] = base + below;
-            if (below == 0)
-                s_wave[wave][dig[i]] = base + __popcll(peers);
-        }
-        __builtin_amdgcn_wave_barrier();
+        const uint32_t below = (uint32_t)__popcll(peers & lt);
+        const uint32_t first = valid ? (uint32_t)(__ffsll((unsigned long long)peers) - 1) : lane;
+        uint32_t base = 0;
+        if (valid && below == 0)
+            base = atomicAdd(&s_wave[wave][dig[i]], (uint32_t)__popcll(peers));
+        rank[i] = base;
+        dig[i] |= (below << 16) | (first << 24);
+    }
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+        rank[i] = __shfl(rank[i], (int)(dig[i] >> 24), 64) + ((dig[i] >> 16) & 0xFFu);
+        dig[i] &= 0xFFFFu;
     }
     __syncthreads();
     // per digit: exclusive offsets across waves and the tile count
@@ -623,7 +637,7 @@ __global__ __launch_bounds__(BLOCK) void k_digit_pass(uint32_t pass, uint32_t sh
         uint32_t sum = 0;
 #pragma unroll
         for (uint32_t w = 0; w < WAVES; w++) {
-            uint32_t v = s_wave[w][d];
+            const uint32_t v = s_wave[w][d];
             s_wave[w][d] = sum;
             sum += v;
         }
@@ -639,55 +653,71 @@ __global__ __launch_bounds__(BLOCK) void k_digit_pass(uint32_t pass, uint32_t sh
         uint32_t local = 0;
 #pragma unroll
         for (uint32_t j = 0; j < PER; j++) {
-            uint32_t d = lane * PER + j;
+            const uint32_t d = lane * PER + j;
             vals[j] = d < RADIX ? s_count[d] : 0;
             local += vals[j];
         }
         uint32_t incl = local;
 #pragma unroll
         for (uint32_t off = 1; off < 64; off <<= 1) {
-            uint32_t up = __shfl_up(incl, off, 64);
+            const uint32_t up = __shfl_up(incl, off, 64);
             if (lane >= off)
                 incl += up;
         }
         uint32_t run = incl - local;
 #pragma unroll
         for (uint32_t j = 0; j < PER; j++) {
-            uint32_t d = lane * PER + j;
+            const uint32_t d = lane * PER + j;
             if (d < RADIX)
                 s_start[d] = run;
             run += vals[j];
         }
     }
+    __syncthreads();
     // decoupled look-back per digit
     for (uint32_t d = tid; d < RADIX; d += BLOCK) {
         uint32_t excl = 0;
         if (tile != 0) {
             int64_t j = (int64_t)tile - 1;
+            uint32_t spins = 0;
             while (j >= 0) {
-                uint32_t v = ld_agent(&look[(size_t)j * RADIX + d]);
-                uint32_t f = v & ~kCountMask;
+                const uint32_t v = ld_agent(&look[(size_t)j * RADIX + d]);
+                const uint32_t f = v & ~kCountMask;
                 if (f == 0) {
-                    __builtin_amdgcn_s_sleep(1);
+                    if (++spins <= kSpinLimit) {
+                        __builtin_amdgcn_s_sleep(1);
+                        continue;
+                    }
+                    // predecessor not running yet: count its digit d directly
+                    const uint64_t b0 = (uint64_t)j * TILE;
+                    const uint64_t b1 = min<uint64_t>(b0 + TILE, (uint64_t)n);
+                    uint32_t c = 0;
+                    for (uint64_t q = b0; q < b1; q++)
+                        c += ((uint32_t)(kin[q] >> shift) & (RADIX - 1u)) == d;
+                    excl += c;
+                    j--;
+                    spins = 0;
                     continue;
                 }
                 excl += v & kCountMask;
                 if (f == kFlagPrefix)
                     break;
                 j--;
+                spins = 0;
             }
             st_agent(&look[(size_t)tile * RADIX + d], kFlagPrefix | (excl + s_count[d]));
         }
-        s_gbase[d] = dbase[d] + excl;
+        s_delta[d] = (int32_t)(dbase[d] + excl) - (int32_t)s_start[d];
     }
-    __syncthreads();
     // stage the tile in LDS grouped by digit (stable)
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
         if (dig[i] < RADIX) {
             const uint32_t pos = s_start[dig[i]] + s_wave[wave][dig[i]] + rank[i];
-            s_keys[pos] = key[i];
-            s_idx[pos] = idx[i];
+            KV<KeyT> kv;
+            kv.key = key[i];
+            kv.idx = idx[i];
+            s_kv[pos] = kv;
         }
     }
     __syncthreads();
@@ -696,13 +726,13 @@ __global__ __launch_bounds__(BLOCK) void k_digit_pass(uint32_t pass, uint32_t sh
     for (int i = 0; i < ITEMS; i++) {
         const uint32_t j = tid + i * BLOCK;
         if (j < valid_n) {
-            const KeyT k = s_keys[j];
-            const uint32_t d = (uint32_t)(k >> shift) & (RADIX - 1u);
-            const uint32_t g = s_gbase[d] + (j - s_start[d]);
+            const KV<KeyT> kv = s_kv[j];
+            const uint32_t d = (uint32_t)(kv.key >> shift) & (RADIX - 1u);
+            const uint32_t g = (uint32_t)((int32_t)j + s_delta[d]);
             if (g < n) {
                 if (!ps.last)
-                    kout[g] = k;
-                iout[g] = s_idx[j];
+                    kout[g] = kv.key;
+                iout[g] = kv.idx;
             }
         }
     }
@@ -777,8 +807,8 @@ static inline void mark(Prof* prof, hipStream_t s, int32_t stage);
 template <typename KeyT, int RB>
 static hipError_t launch_passes_rb(const Plan& P, char* ws, hipStream_t s, Prof* prof)
 {
-    constexpr int BLOCK = 256;
-    constexpr int ITEMS = sizeof(KeyT) == 8 ? 8 : 16;
+    constexpr int BLOCK = kPassBlock;
+    constexpr int ITEMS = PassItems<KeyT>::value;
     constexpr uint32_t RADIX = 1u << RB;
     mark(prof, s, kStageSchedule);
     hipLaunchKernelGGL((k_schedule<RB>), dim3(1), dim3(256), 0, s,
