@@ -115,6 +115,46 @@ int pbit_sort_list_profiled(uint32_t head, const uint32_t *next_in, uint32_t *ne
  * "end"). */
 const char *pbit_stage_name(int stage);
 
+/*
+ * Many independent lists sorted in one launch sequence (the batched form).
+ * The lists share next_in/next_out/keys: list l owns the node slab
+ * [d_offsets[l], d_offsets[l+1]) and its next[] entries are global node
+ * indices inside that slab (Sec. 3 applied to every list on its own).
+ *   d_heads     uint32[num_lists]   first node of each list, PBIT_NIL for an
+ *                                   empty slab (device memory)
+ *   d_offsets   uint64[num_lists+1] slab bounds, d_offsets[0] = 0,
+ *                                   non-decreasing, d_offsets[num_lists] =
+ *                                   total_nodes (device memory)
+ *   next_in/next_out/keys           as for pbit_sort_list_async, over
+ *                                   total_nodes < 2^32 - 1 nodes
+ *   d_new_heads uint32[num_lists]   receives each list's new head
+ *   d_status    int32               receives PBIT_OK, PBIT_EMALFORMED (some
+ *                                   list is not a single NIL-terminated list
+ *                                   inside its slab) or PBIT_EINVAL (bad slab
+ *                                   bounds or head); on error next_out and
+ *                                   d_new_heads are not written
+ * Each list comes out exactly as pbit_sort_list_async would sort it alone.
+ * ws holds at least pbit_lists_workspace_bytes(total_nodes, num_lists, M, K)
+ * bytes.  Nothing is allocated; the call may be captured in a HIP graph.
+ * Returns PBIT_OK once queued, or a host-side error (nothing queued).
+ */
+size_t pbit_lists_workspace_bytes(uint64_t total_nodes, uint32_t num_lists, uint32_t M,
+                                  uint32_t K);
+
+int pbit_sort_lists(const uint32_t *d_heads, const uint64_t *d_offsets, uint32_t num_lists,
+                    uint64_t total_nodes, const uint32_t *next_in, uint32_t *next_out,
+                    const void *keys, uint32_t M, uint32_t K, uint32_t flags,
+                    uint32_t *d_new_heads, int32_t *d_status, void *ws, size_t ws_bytes,
+                    void *stream);
+
+/* Measurement form of pbit_sort_lists (see pbit_sort_list_profiled). */
+int pbit_sort_lists_profiled(const uint32_t *d_heads, const uint64_t *d_offsets,
+                             uint32_t num_lists, uint64_t total_nodes, const uint32_t *next_in,
+                             uint32_t *next_out, const void *keys, uint32_t M, uint32_t K,
+                             uint32_t flags, uint32_t *d_new_heads, int32_t *d_status, void *ws,
+                             size_t ws_bytes, void *stream, void **events, int32_t *stage_ids,
+                             int n_events, int *n_recorded);
+
 /* Human-readable text for a status code. */
 const char *pbit_status_string(int code);
 

@@ -33,6 +33,17 @@ _SIGNATURES = {
         ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
         ctypes.POINTER(ctypes.c_int)]),
     "pbit_stage_name": (ctypes.c_char_p, [ctypes.c_int]),
+    "pbit_lists_workspace_bytes": (ctypes.c_size_t, [ctypes.c_uint64, ctypes.c_uint32,
+                                                     ctypes.c_uint32, ctypes.c_uint32]),
+    "pbit_sort_lists": (ctypes.c_int, [
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p,
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "pbit_sort_lists_profiled": (ctypes.c_int, [
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p,
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "pbit_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "pbit_version": (ctypes.c_char_p, []),
 }
@@ -88,6 +99,19 @@ def sort_list_async(head: int, next_in, next_out, keys, n: int, M: int, K: int, 
     return int(load().pbit_sort_list_async(
         int(head) & 0xFFFFFFFF, _ptr(next_in), _ptr(next_out), _ptr(keys), int(n), int(M),
         int(K), int(flags), _ptr(result), _ptr(ws), int(ws_bytes), _stream_handle(stream)))
+
+
+def lists_workspace_bytes(total: int, num_lists: int, M: int, K: int = 0) -> int:
+    return int(load().pbit_lists_workspace_bytes(total, num_lists, M, K))
+
+
+def sort_lists(heads, offsets, num_lists: int, total: int, next_in, next_out, keys, M: int,
+               K: int, flags: int, new_heads, status, ws, ws_bytes: int, stream=None) -> int:
+    """Raw C-ABI call of the batched form with device tensors."""
+    return int(load().pbit_sort_lists(
+        _ptr(heads), _ptr(offsets), int(num_lists), int(total), _ptr(next_in), _ptr(next_out),
+        _ptr(keys), int(M), int(K), int(flags), _ptr(new_heads), _ptr(status), _ptr(ws),
+        int(ws_bytes), _stream_handle(stream)))
 
 
 def sort_list(head: int, next_, keys, M: int, K: int = 0) -> int:

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpbit.so")
-SOURCES = ["pbit_kernels.hip", "pbit_capi.hip"]
+SOURCES = ["pbit_kernels.hip", "pbit_forest.hip", "pbit_capi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -14,14 +14,20 @@ namespace pbit {
 hipError_t enqueue_sort(const Plan& P, uint32_t head, const uint32_t* next_in, uint32_t* next_out,
                         const void* keys, uint32_t* d_result, char* ws, hipStream_t s, Prof* prof);
 hipError_t enqueue_empty(uint32_t* d_result, hipStream_t s);
-size_t entry_bytes(uint32_t key_bytes);
-size_t node_bytes(uint32_t key_bytes);
-size_t chain_cap();
+hipError_t enqueue_sort_lists(const Plan& P, const uint32_t* heads, const uint64_t* offsets,
+                              const uint32_t* next_in, uint32_t* next_out, const void* keys,
+                              uint32_t* new_heads, int32_t* d_status, char* ws, hipStream_t s,
+                              Prof* prof);
 uint32_t pass_tile(uint32_t key_bytes);
 
 static size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
 static uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+static size_t entry_bytes(uint32_t key_bytes) { return key_bytes == 8 ? 16 : 8; }
+static size_t node_bytes(uint32_t key_bytes) { return key_bytes == 8 ? 16 : 8; }
+// Entries a level-0 walker keeps in registers (matches the device SegLen).
+static uint32_t reg_entries(uint32_t key_bytes) { return key_bytes == 8 ? 16 : 32; }
 
 // Pattern width when the caller leaves it to the library.
 static uint32_t default_k(uint32_t M) { return M == 8 ? 4u : 8u; }
@@ -32,34 +38,32 @@ static bool valid_shape(uint32_t M, uint32_t K)
         return false;
     if (K != 0 && K != 1 && K != 2 && K != 4 && K != 8)
         return false;
-    uint32_t k = K ? K : default_k(M);
+    const uint32_t k = K ? K : default_k(M);
     return (M % k) == 0;
 }
 
-// Workspace layout for one list.  Returns false on arguments the C ABI rejects.
-bool make_plan(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, Plan* P)
+// Regions every sort uses: header, histograms, look-back words, packed
+// nodes, the two list-order buffers and the level-0 chain arrays.
+static bool plan_common(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, uint32_t lid_passes,
+                        size_t lw_bytes, uint64_t level0_chains, uint32_t cap, Plan* P, size_t& off)
 {
-    memset(P, 0, sizeof(*P));
     if (!valid_shape(M, K) || (flags & ~(uint32_t)(PBIT_DESCENDING | PBIT_SIGNED)) != 0)
-        return false;
-    if (n > PBIT_MAX_NODES)
         return false;
     P->n = n;
     P->M = M;
     P->K = K ? K : default_k(M);
     P->RB = P->K;
     P->radix = 1u << P->K;
-    P->passes = M / P->K;
+    P->key_passes = M / P->K;
+    P->passes = P->key_passes + lid_passes;
+    if (P->passes > (uint32_t)kMaxPasses)
+        return false;
     P->flags = flags;
     P->key_bytes = M / 8;
     P->tile = pass_tile(P->key_bytes);
     P->items = P->tile / 512;
     P->tiles = (uint32_t)ceil_div(n ? n : 1, P->tile);
-    if (n == 0) {
-        P->total = 256;
-        return true;
-    }
-    size_t off = 0;
+    off = 0;
     P->o_header = off;
     off = align_up(off + sizeof(Header));
     P->o_hist = off;
@@ -67,7 +71,7 @@ bool make_plan(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, Plan* P)
     P->o_dbase = off;
     off = align_up(off + (size_t)P->passes * P->radix * 4);
     P->o_look = off;
-    off = align_up(off + (size_t)P->passes * P->tiles * P->radix * 4);
+    off = align_up(off + (size_t)P->passes * P->tiles * P->radix * lw_bytes);
     P->zero_end = off;
     P->o_nodes = off;
     off = align_up(off + n * node_bytes(P->key_bytes));
@@ -79,32 +83,111 @@ bool make_plan(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, Plan* P)
     off = align_up(off + n * P->key_bytes);
     P->o_idxB = off;
     off = align_up(off + n * 4);
+    LevelPlan& L = P->lv[0];
+    L.log_l = kLog0;
+    L.m = n;
+    L.n_static = level0_chains;
+    L.cap = cap;
+    L.o_chain_rec = off;
+    off = align_up(off + L.n_static * 8);
+    L.o_ent = off;
+    off = align_up(off + L.n_static * cap * entry_bytes(P->key_bytes));
+    L.o_resume = off;
+    off = align_up(off + L.n_static * 4);
+    L.o_offn = off;
+    off = align_up(off + L.n_static * 4);
+    return true;
+}
 
-    int k = 0;
-    uint64_t m = n;
-    for (;;) {
+// Workspace layout for one list.  Returns false on arguments the C ABI rejects.
+bool make_plan(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, Plan* P)
+{
+    memset(P, 0, sizeof(*P));
+    if (n > PBIT_MAX_NODES || !valid_shape(M, K))
+        return false;
+    if (n == 0) {
+        size_t off;
+        if (!plan_common(0, M, K, flags, 0, 4, 0, 0, P, off))
+            return false;
+        P->total = 256;
+        return true;
+    }
+    const uint32_t reg = reg_entries(M / 8);
+    const uint32_t cap = n <= (1ull << 26) ? 128u : reg;
+    size_t off = 0;
+    if (!plan_common(n, M, K, flags, 0, 4, 1 + ceil_div(n, 1ull << kLog0), cap, P, off))
+        return false;
+    int k = 1;
+    uint64_t m = P->lv[0].n_static;
+    while (m > kBaseMax) {
         if (k >= kMaxLevels)
             return false;
         LevelPlan& L = P->lv[k];
-        L.log_l = k == 0 ? kLog0 : kLogUp;
+        L.log_l = kLogUp;
         L.m = m;
         L.n_static = 1 + ceil_div(m, 1ull << L.log_l);
         L.o_chain_rec = off;
         off = align_up(off + L.n_static * 8);
-        if (k == 0) {
-            L.o_ent = off;
-            off = align_up(off + L.n_static * chain_cap() * entry_bytes(P->key_bytes));
-            L.o_resume = off;
-            off = align_up(off + L.n_static * 4);
-        }
         L.o_offn = off;
         off = align_up(off + L.n_static * 4);
-        k++;
         m = L.n_static;
-        if (m <= kBaseMax)
-            break;
+        k++;
     }
     P->levels = k;
+    P->total = off;
+    return true;
+}
+
+static uint32_t bits_for(uint64_t x)
+{
+    uint32_t b = 0;
+    while (x) {
+        b++;
+        x >>= 1;
+    }
+    return b;
+}
+
+// Workspace layout for num_lists lists over n nodes in total.
+bool make_plan_lists(uint64_t n, uint32_t num_lists, uint32_t M, uint32_t K, uint32_t flags,
+                     Plan* P)
+{
+    memset(P, 0, sizeof(*P));
+    if (num_lists == 0 || n >= (uint64_t)PBIT_NIL || !valid_shape(M, K))
+        return false;
+    const uint32_t k = K ? K : default_k(M);
+    const uint32_t lid_passes = (uint32_t)ceil_div(bits_for(num_lists - 1) ? bits_for(num_lists - 1) : 1, k);
+    const uint32_t reg = reg_entries(M / 8);
+    const uint32_t cap = n <= (1ull << 26) ? 128u : reg;
+    const uint64_t chains0 = (uint64_t)num_lists + ceil_div(n, 1ull << kLog0);
+    if (chains0 >= (uint64_t)PBIT_NIL)
+        return false;
+    size_t off = 0;
+    if (!plan_common(n, M, K, flags, lid_passes, 8, chains0, cap, P, off))
+        return false;
+    P->num_lists = num_lists;
+    P->log_block = 8;
+    P->o_table = off;
+    off = align_up(off + (ceil_div(n, 1ull << P->log_block) + 1) * 4);
+    P->o_headbits = off;  // cleared by its own launch at the start of every sort
+    off = align_up(off + (ceil_div(n, 32) + 1) * 4);
+    int lv = 1;
+    uint64_t m = chains0;
+    while (m > num_lists) {
+        if (lv >= kMaxLevels)
+            return false;
+        LevelPlan& L = P->lv[lv];
+        L.log_l = 3;
+        L.m = m;
+        L.n_static = num_lists + (m - num_lists) / 8;
+        L.o_chain_rec = off;
+        off = align_up(off + L.n_static * 8);
+        L.o_offn = off;
+        off = align_up(off + L.n_static * 4);
+        m = L.n_static;
+        lv++;
+    }
+    P->levels = lv;
     P->total = off;
     return true;
 }
@@ -238,6 +321,67 @@ extern "C" int64_t pbit_sort_list(uint32_t head, uint32_t* next, const void* key
     if ((int32_t)res[1] != 0)
         return (int32_t)res[1];
     return (int64_t)res[0];
+}
+
+extern "C" size_t pbit_lists_workspace_bytes(uint64_t total_nodes, uint32_t num_lists, uint32_t M,
+                                             uint32_t K)
+{
+    Plan P;
+    if (!make_plan_lists(total_nodes, num_lists, M, K, 0, &P))
+        return 0;
+    return P.total;
+}
+
+static int sort_lists_impl(const uint32_t* d_heads, const uint64_t* d_offsets, uint32_t num_lists,
+                           uint64_t total_nodes, const uint32_t* next_in, uint32_t* next_out,
+                           const void* keys, uint32_t M, uint32_t K, uint32_t flags,
+                           uint32_t* d_new_heads, int32_t* d_status, void* ws, size_t ws_bytes,
+                           void* stream, Prof* prof)
+{
+    Plan P;
+    if (!make_plan_lists(total_nodes, num_lists, M, K, flags, &P))
+        return PBIT_EINVAL;
+    if (!d_heads || !d_offsets || !d_new_heads || !d_status || !ws)
+        return PBIT_EINVAL;
+    if (total_nodes > 0 && (!next_in || !next_out || !keys))
+        return PBIT_EINVAL;
+    if (((uintptr_t)d_heads & 3u) || ((uintptr_t)d_offsets & 7u) || ((uintptr_t)d_new_heads & 3u) ||
+        ((uintptr_t)d_status & 3u) || ((uintptr_t)next_in & 3u) || ((uintptr_t)next_out & 3u) ||
+        ((uintptr_t)keys & (P.key_bytes - 1)) || ((uintptr_t)ws & 255u))
+        return PBIT_EINVAL;
+    if (ws_bytes < P.total)
+        return PBIT_ENOMEM;
+    hipError_t e = enqueue_sort_lists(P, d_heads, d_offsets, next_in, next_out, keys, d_new_heads,
+                                      d_status, (char*)ws, (hipStream_t)stream, prof);
+    return e == hipSuccess ? PBIT_OK : PBIT_EHIP;
+}
+
+extern "C" int pbit_sort_lists(const uint32_t* d_heads, const uint64_t* d_offsets,
+                               uint32_t num_lists, uint64_t total_nodes, const uint32_t* next_in,
+                               uint32_t* next_out, const void* keys, uint32_t M, uint32_t K,
+                               uint32_t flags, uint32_t* d_new_heads, int32_t* d_status, void* ws,
+                               size_t ws_bytes, void* stream)
+{
+    return sort_lists_impl(d_heads, d_offsets, num_lists, total_nodes, next_in, next_out, keys, M,
+                           K, flags, d_new_heads, d_status, ws, ws_bytes, stream, nullptr);
+}
+
+extern "C" int pbit_sort_lists_profiled(const uint32_t* d_heads, const uint64_t* d_offsets,
+                                        uint32_t num_lists, uint64_t total_nodes,
+                                        const uint32_t* next_in, uint32_t* next_out,
+                                        const void* keys, uint32_t M, uint32_t K, uint32_t flags,
+                                        uint32_t* d_new_heads, int32_t* d_status, void* ws,
+                                        size_t ws_bytes, void* stream, void** events,
+                                        int32_t* stage_ids, int n_events, int* n_recorded)
+{
+    if (!events || n_events <= 0 || !n_recorded)
+        return PBIT_EINVAL;
+    Prof prof{events, stage_ids, n_events, 0};
+    const int st = sort_lists_impl(d_heads, d_offsets, num_lists, total_nodes, next_in, next_out,
+                                   keys, M, K, flags, d_new_heads, d_status, ws, ws_bytes, stream,
+                                   &prof);
+    *n_recorded = prof.count;
+    return st;
 }
 
 extern "C" const char* pbit_status_string(int code)

@@ -1,0 +1,523 @@
+// Device code shared by the single-list path (pbit_kernels.hip) and the
+// many-list path (pbit_forest.hip): node records, hashing, the pack kernel,
+// chain unloading, the pass schedule and the stable digit pass.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "pbit.h"
+#include "pbit_internal.h"
+
+namespace pbit {
+
+// ---------------------------------------------------------------- records
+// Packed node record: next and key in one load (8 bytes, 16 for u64 keys).
+template <typename KeyT> struct NodeRec { uint32_t next; uint32_t key; };
+template <> struct __attribute__((aligned(16))) NodeRec<uint64_t> { uint32_t next; uint32_t pad; uint64_t key; };
+
+// (key, node) entry of a level-0 chain.
+template <typename KeyT> struct Entry { uint32_t key; uint32_t idx; };
+template <> struct __attribute__((aligned(16))) Entry<uint64_t> { uint64_t key; uint32_t idx; uint32_t pad; };
+
+template <typename KeyT> __device__ __forceinline__ KeyT entry_key(const Entry<KeyT>& e) { return (KeyT)e.key; }
+
+// Entries of a level-0 chain kept in registers by its walker.
+template <typename KeyT> struct SegLen { static constexpr uint32_t value = sizeof(KeyT) == 8 ? 16 : 32; };
+
+// Digit-pass tile: kPassBlock threads x PassItems items.
+constexpr int kPassBlock = 512;
+template <typename KeyT> struct PassItems { static constexpr int value = sizeof(KeyT) == 8 ? 8 : 16; };
+
+__device__ __forceinline__ void set_error(int32_t* status, int32_t code)
+{
+    atomicCAS(status, 0, code);
+}
+
+template <typename T> __device__ __forceinline__ T ld_agent(const T* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T> __device__ __forceinline__ void st_agent(T* p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt()
+{
+    const uint32_t lane = __lane_id();
+    return (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+}
+
+// ---------------------------------------------------------------- init
+static __global__ void k_zero(uint32_t* __restrict__ p, size_t words)
+{
+    size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < words; i += stride)
+        p[i] = 0u;
+}
+
+// ---------------------------------------------------------------- hashing
+// In-degree check: over a valid list (or set of lists) the non-NIL next[]
+// values are every node except the heads, each once.  The sum of a 64-bit
+// mixing hash over them must equal the sum over all nodes minus the heads.
+__device__ __forceinline__ uint64_t mix64(uint64_t x, uint64_t k)
+{
+    x ^= x >> 31;
+    x *= k;
+    x ^= x >> 29;
+    x *= 0xBF58476D1CE4E5B9ull;
+    x ^= x >> 32;
+    return x;
+}
+constexpr uint64_t kHashK1 = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kHashK2 = 0xD6E8FEB86659FD93ull;
+
+// ---------------------------------------------------------------- pack
+// Node records, the count of every pattern value of every key pass, the NIL
+// count and the hash sums sum h(next) - sum h(i).
+template <typename KeyT, int RB>
+__global__ __launch_bounds__(256) void k_pack(const uint32_t* __restrict__ next,
+                                              const KeyT* __restrict__ keys, uint32_t n,
+                                              KeyT xor_mask, uint32_t passes,
+                                              NodeRec<KeyT>* __restrict__ nodes,
+                                              uint32_t* __restrict__ hist, Header* hdr)
+{
+    constexpr uint32_t RADIX = 1u << RB;
+    extern __shared__ uint32_t s_hist[];  // passes * RADIX
+    const uint32_t nbins = passes * RADIX;
+    for (uint32_t i = threadIdx.x; i < nbins; i += blockDim.x)
+        s_hist[i] = 0;
+    __syncthreads();
+    bool bad = false;
+    uint64_t h1 = 0, h2 = 0;
+    uint32_t nils = 0;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t nx = next[i];
+        const KeyT k = keys[i] ^ xor_mask;
+        bad |= (nx != kNil) && (nx >= n);
+        if (nx == kNil) {
+            nils++;
+        } else {
+            h1 += mix64(nx + 1ull, kHashK1);
+            h2 += mix64(nx + 1ull, kHashK2);
+        }
+        h1 -= mix64(i + 1ull, kHashK1);
+        h2 -= mix64(i + 1ull, kHashK2);
+        NodeRec<KeyT> r;
+        r.next = nx;
+        r.key = k;
+        if constexpr (sizeof(KeyT) == 8) r.pad = 0;
+        nodes[i] = r;
+        for (uint32_t p = 0; p < passes; p++) {
+            const uint32_t d = (uint32_t)(k >> (p * RB)) & (RADIX - 1u);
+            atomicAdd(&s_hist[p * RADIX + d], 1u);
+        }
+    }
+    if (bad)
+        set_error(&hdr->status, PBIT_EMALFORMED);
+    for (int off = 32; off > 0; off >>= 1) {
+        h1 += (uint64_t)__shfl_xor((unsigned long long)h1, off, 64);
+        h2 += (uint64_t)__shfl_xor((unsigned long long)h2, off, 64);
+        nils += __shfl_xor(nils, off, 64);
+    }
+    __shared__ uint64_t s_h[2][4];
+    __shared__ uint32_t s_nil[4];
+    const uint32_t wave = threadIdx.x / 64;
+    if (__lane_id() == 0) {
+        s_h[0][wave] = h1;
+        s_h[1][wave] = h2;
+        s_nil[wave] = nils;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t a = 0, b = 0;
+        uint32_t z = 0;
+        for (uint32_t w = 0; w < blockDim.x / 64; w++) {
+            a += s_h[0][w];
+            b += s_h[1][w];
+            z += s_nil[w];
+        }
+        atomicAdd((unsigned long long*)&hdr->hsum[0], (unsigned long long)a);
+        atomicAdd((unsigned long long*)&hdr->hsum[1], (unsigned long long)b);
+        if (z)
+            atomicAdd(&hdr->nil_count, z);
+    }
+    for (uint32_t i = threadIdx.x; i < nbins; i += blockDim.x) {
+        const uint32_t v = s_hist[i];
+        if (v)
+            atomicAdd(&hist[i], v);
+    }
+}
+
+// ---------------------------------------------------------------- unchain
+// The stored entries of every level-0 chain (up to `cap`) to list order.
+template <typename KeyT>
+__global__ __launch_bounds__(256) void k_unchain(const uint2* __restrict__ chain_rec,
+                                                 const Entry<KeyT>* __restrict__ ent,
+                                                 uint32_t n_chains, uint32_t cap,
+                                                 const uint32_t* __restrict__ offn_chain, uint32_t n,
+                                                 KeyT* __restrict__ keys_l,
+                                                 uint32_t* __restrict__ idx_l, Header* hdr)
+{
+    constexpr uint32_t G = 16;  // threads per chain
+    if (hdr->status != 0)
+        return;
+    const uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    const uint32_t c = (uint32_t)(g / G);
+    if (c >= n_chains)
+        return;
+    const uint32_t len = min(chain_rec[c].y, cap);
+    const uint32_t base = offn_chain[c];
+    const Entry<KeyT>* b = ent + (size_t)c * cap;
+    for (uint32_t t = (uint32_t)(g % G); t < len; t += G) {
+        const uint32_t pos = base + t;
+        if (pos >= n)
+            break;
+        const Entry<KeyT> e = b[t];
+        keys_l[pos] = entry_key<KeyT>(e);
+        idx_l[pos] = e.idx;
+    }
+}
+
+// The rest of every level-0 chain longer than its slot, walked again from
+// its resume node and written straight to list order.
+template <typename KeyT>
+__global__ __launch_bounds__(256) void k_walk2(const NodeRec<KeyT>* __restrict__ nodes,
+                                               const uint2* __restrict__ chain_rec,
+                                               const uint32_t* __restrict__ resume,
+                                               uint32_t n_chains, uint32_t cap,
+                                               const uint32_t* __restrict__ offn_chain, uint32_t n,
+                                               KeyT* __restrict__ keys_l,
+                                               uint32_t* __restrict__ idx_l, Header* hdr)
+{
+    if (hdr->status != 0)
+        return;
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_chains)
+        return;
+    const uint32_t len = chain_rec[c].y;
+    if (len <= cap)
+        return;
+    uint32_t cur = resume[c];
+    uint32_t pos = offn_chain[c] + cap;
+    const uint32_t end = (uint32_t)min<uint64_t>((uint64_t)offn_chain[c] + len, (uint64_t)n);
+    while (pos < end && cur < n) {
+        const NodeRec<KeyT> r = nodes[cur];
+        keys_l[pos] = (KeyT)r.key;
+        idx_l[pos] = cur;
+        pos++;
+        cur = r.next;
+    }
+}
+
+// ---------------------------------------------------------------- schedule
+// Per pass: exclusive scan of the digit counts (global digit bases), whether
+// the pass is the identity (every element has the same digit: the paper's
+// empty groups), which ping-pong buffer it reads, and whether it must still
+// write keys (only while a later key pass runs).  Passes [0, key_passes) split
+// on key patterns, later passes on list ids.
+template <int RB>
+__global__ __launch_bounds__(256) void k_schedule(const uint32_t* __restrict__ hist,
+                                                  uint32_t* __restrict__ dbase, uint32_t passes,
+                                                  uint32_t key_passes, uint32_t n, Header* hdr)
+{
+    constexpr uint32_t RADIX = 1u << RB;
+    __shared__ uint32_t s_v[RADIX];
+    __shared__ uint32_t s_skip[kMaxPasses];
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t p = 0; p < passes; p++) {
+        uint32_t v = 0;
+        if (tid < RADIX) {
+            v = hist[p * RADIX + tid];
+            s_v[tid] = v;
+        }
+        __syncthreads();
+        const int full = (tid < RADIX) && (v == n);
+        const int any_full = __syncthreads_or(full);
+        if (tid == 0) {
+            uint32_t sum = 0;
+            for (uint32_t d = 0; d < RADIX; d++) {
+                const uint32_t x = s_v[d];
+                s_v[d] = sum;
+                sum += x;
+            }
+            s_skip[p] = any_full ? 1u : 0u;
+        }
+        __syncthreads();
+        if (tid < RADIX)
+            dbase[p * RADIX + tid] = s_v[tid];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        int last_key = -1;
+        for (uint32_t p = 0; p < key_passes; p++)
+            if (!s_skip[p])
+                last_key = (int)p;
+        uint32_t cur = 0;
+        for (uint32_t p = 0; p < passes; p++) {
+            PassSched ps;
+            ps.skip = s_skip[p];
+            ps.in_buf = cur;
+            ps.write_keys = (int)p < last_key ? 1u : 0u;
+            ps.pad = 0;
+            if (!ps.skip)
+                cur ^= 1u;
+            hdr->sched[p] = ps;
+        }
+        hdr->final_buf = cur;
+    }
+}
+
+// ---------------------------------------------------------------- digit pass
+// One stable split on the pattern at bit `shift`.  A tile of BLOCK * ITEMS
+// consecutive list positions (tile = block index) is loaded wave-striped,
+// ranked per wave (K ballots give each item the mask of lanes with the same
+// digit; the first lane of each group adds the group size to a wave-private
+// LDS counter with one in-order LDS atomic, and peers take the returned base
+// from it), scanned across waves, chained across tiles by decoupled look-back
+// (Merrill & Garland), staged in LDS grouped by digit and written out in
+// runs.  The look-back spin is bounded: a tile that waits too long on a
+// predecessor counts that predecessor's digit in its input itself, so no
+// tile ever waits on a tile that has not been scheduled.
+//
+// LW is the look-back word: 2 flag bits over a 30-bit count (uint32_t, for
+// n < 2^30) or 2 flag bits over a 32-bit count (uint64_t).  With LID the
+// digit is taken from the list id of the node (many-list sorts); keys are
+// then neither read nor written.
+template <typename LW> struct Look;
+template <> struct Look<uint32_t> {
+    static constexpr uint32_t AGG = 1u << 30, PREFIX = 2u << 30, MASK = (1u << 30) - 1u;
+};
+template <> struct Look<uint64_t> {
+    static constexpr uint64_t AGG = 1ull << 32, PREFIX = 2ull << 32, MASK = 0xFFFFFFFFull;
+};
+
+// Node -> list of a many-list sort: lists own contiguous node slabs
+// [offsets[l], offsets[l+1]); table[b] is the list holding node b << log_block.
+struct LidMap {
+    const uint32_t* table;
+    const uint64_t* offsets;
+    uint32_t num_lists;
+    uint32_t log_block;
+};
+
+__device__ __forceinline__ uint32_t list_of(const LidMap& lm, uint32_t node)
+{
+    uint32_t l = min(lm.table[node >> lm.log_block], lm.num_lists - 1u);
+    while (l + 1 < lm.num_lists && lm.offsets[l + 1] <= node)
+        l++;
+    return l;
+}
+
+template <typename SKey> struct KV { SKey key; uint32_t idx; };
+
+constexpr uint32_t kSpinLimit = 4096;
+
+template <typename KeyT, int RB, int BLOCK, int ITEMS, typename LW, bool LID>
+__global__ __launch_bounds__(BLOCK, 4) void k_digit_pass(uint32_t pass, uint32_t shift, uint32_t n,
+                                                         KeyT* __restrict__ keysA,
+                                                         uint32_t* __restrict__ idxA,
+                                                         KeyT* __restrict__ keysB,
+                                                         uint32_t* __restrict__ idxB,
+                                                         const uint32_t* __restrict__ dbase,
+                                                         LW* __restrict__ look, Header* hdr,
+                                                         LidMap lm)
+{
+    using SKey = typename std::conditional<LID, uint32_t, KeyT>::type;
+    using LK = Look<LW>;
+    constexpr uint32_t RADIX = 1u << RB;
+    constexpr uint32_t WAVES = BLOCK / 64;
+    constexpr uint32_t TILE = BLOCK * ITEMS;
+    __shared__ uint32_t s_wave[WAVES][RADIX];
+    __shared__ uint32_t s_count[RADIX];
+    __shared__ uint32_t s_start[RADIX];
+    __shared__ uint32_t s_delta[RADIX];
+    __shared__ KV<SKey> s_kv[TILE];
+
+    if (hdr->status != 0)
+        return;
+    const PassSched ps = hdr->sched[pass];
+    if (ps.skip)
+        return;
+    const KeyT* kin = ps.in_buf ? keysB : keysA;
+    const uint32_t* iin = ps.in_buf ? idxB : idxA;
+    KeyT* kout = ps.in_buf ? keysA : keysB;
+    uint32_t* iout = ps.in_buf ? idxA : idxB;
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t wave = tid / 64, lane = tid % 64;
+    for (uint32_t i = tid; i < WAVES * RADIX; i += BLOCK)
+        (&s_wave[0][0])[i] = 0;
+    __syncthreads();
+    const uint32_t tile = blockIdx.x;
+    const uint64_t tbase = (uint64_t)tile * TILE;
+    const uint64_t wbase = tbase + (uint64_t)wave * (64 * ITEMS);
+
+    SKey key[ITEMS];
+    uint32_t idx[ITEMS], dig[ITEMS], rank[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+        const uint64_t e = wbase + (uint64_t)i * 64 + lane;
+        if (e < n) {
+            idx[i] = iin[e];
+            if constexpr (LID)
+                key[i] = list_of(lm, idx[i]);
+            else
+                key[i] = kin[e];
+            dig[i] = (uint32_t)(key[i] >> shift) & (RADIX - 1u);
+        } else {
+            key[i] = 0;
+            idx[i] = 0;
+            dig[i] = RADIX;
+        }
+    }
+    // dig[i] bits: 0..8 digit (RADIX = invalid), 16..21 rank in the wave's
+    // group, 24..29 the group's first lane (which holds the LDS base)
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+        const bool valid = dig[i] < RADIX;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < RB; b++) {
+            const bool bit = (dig[i] >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            peers &= bit ? bb : ~bb;
+        }
+        const uint32_t below = (uint32_t)__popcll(peers & lt);
+        const uint32_t first = valid ? (uint32_t)(__ffsll((unsigned long long)peers) - 1) : lane;
+        uint32_t base = 0;
+        if (valid && below == 0)
+            base = atomicAdd(&s_wave[wave][dig[i]], (uint32_t)__popcll(peers));
+        rank[i] = base;
+        dig[i] |= (below << 16) | (first << 24);
+    }
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+        rank[i] = __shfl(rank[i], (int)(dig[i] >> 24), 64) + ((dig[i] >> 16) & 0xFFu);
+        dig[i] &= 0xFFFFu;
+    }
+    __syncthreads();
+    // per digit: exclusive offsets across waves and the tile count
+    for (uint32_t d = tid; d < RADIX; d += BLOCK) {
+        uint32_t sum = 0;
+#pragma unroll
+        for (uint32_t w = 0; w < WAVES; w++) {
+            const uint32_t v = s_wave[w][d];
+            s_wave[w][d] = sum;
+            sum += v;
+        }
+        s_count[d] = sum;
+        // publish this tile's count early so successors can proceed
+        st_agent(&look[(size_t)tile * RADIX + d], (tile == 0 ? LK::PREFIX : LK::AGG) | (LW)sum);
+    }
+    __syncthreads();
+    // local digit starts (exclusive scan over digits) by wave 0
+    if (wave == 0) {
+        constexpr uint32_t PER = (RADIX + 63) / 64;
+        uint32_t vals[PER];
+        uint32_t local = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < PER; j++) {
+            const uint32_t d = lane * PER + j;
+            vals[j] = d < RADIX ? s_count[d] : 0;
+            local += vals[j];
+        }
+        uint32_t incl = local;
+#pragma unroll
+        for (uint32_t off = 1; off < 64; off <<= 1) {
+            const uint32_t up = __shfl_up(incl, off, 64);
+            if (lane >= off)
+                incl += up;
+        }
+        uint32_t run = incl - local;
+#pragma unroll
+        for (uint32_t j = 0; j < PER; j++) {
+            const uint32_t d = lane * PER + j;
+            if (d < RADIX)
+                s_start[d] = run;
+            run += vals[j];
+        }
+    }
+    __syncthreads();
+    // decoupled look-back per digit
+    for (uint32_t d = tid; d < RADIX; d += BLOCK) {
+        uint32_t excl = 0;
+        if (tile != 0) {
+            int64_t j = (int64_t)tile - 1;
+            uint32_t spins = 0;
+            while (j >= 0) {
+                const LW v = ld_agent(&look[(size_t)j * RADIX + d]);
+                const LW f = v & ~LK::MASK;
+                if (f == 0) {
+                    if (++spins <= kSpinLimit) {
+                        __builtin_amdgcn_s_sleep(1);
+                        continue;
+                    }
+                    // predecessor not running yet: count its digit d directly
+                    const uint64_t b0 = (uint64_t)j * TILE;
+                    const uint64_t b1 = min<uint64_t>(b0 + TILE, (uint64_t)n);
+                    uint32_t c = 0;
+                    for (uint64_t q = b0; q < b1; q++) {
+                        uint32_t x;
+                        if constexpr (LID)
+                            x = list_of(lm, iin[q]);
+                        else
+                            x = (uint32_t)(kin[q] >> shift);
+                        if constexpr (LID)
+                            x >>= shift;
+                        c += (x & (RADIX - 1u)) == d;
+                    }
+                    excl += c;
+                    j--;
+                    spins = 0;
+                    continue;
+                }
+                excl += (uint32_t)(v & LK::MASK);
+                if (f == LK::PREFIX)
+                    break;
+                j--;
+                spins = 0;
+            }
+            st_agent(&look[(size_t)tile * RADIX + d], LK::PREFIX | (LW)(excl + s_count[d]));
+        }
+        // wrapping u32 arithmetic: position = j + (base - local start)
+        s_delta[d] = dbase[d] + excl - s_start[d];
+    }
+    // stage the tile in LDS grouped by digit (stable)
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+        if (dig[i] < RADIX) {
+            const uint32_t pos = s_start[dig[i]] + s_wave[wave][dig[i]] + rank[i];
+            KV<SKey> kv;
+            kv.key = key[i];
+            kv.idx = idx[i];
+            s_kv[pos] = kv;
+        }
+    }
+    __syncthreads();
+    const uint32_t valid_n = (uint32_t)min<uint64_t>((uint64_t)TILE, (uint64_t)n - tbase);
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+        const uint32_t j = tid + i * BLOCK;
+        if (j < valid_n) {
+            const KV<SKey> kv = s_kv[j];
+            const uint32_t d = (uint32_t)(kv.key >> shift) & (RADIX - 1u);
+            const uint32_t g = j + s_delta[d];
+            if (g < n) {
+                if constexpr (!LID) {
+                    if (ps.write_keys)
+                        kout[g] = kv.key;
+                }
+                iout[g] = kv.idx;
+            }
+        }
+    }
+}
+
+}  // namespace pbit

@@ -15,7 +15,7 @@ constexpr uint32_t kLogUp = 3;
 // The last level is ranked inside one workgroup's LDS.
 constexpr uint32_t kBaseMax = 8192;
 constexpr int kMaxLevels = 12;
-constexpr int kMaxPasses = 64;
+constexpr int kMaxPasses = 96;
 
 // Lookback words: 2 flag bits + 30-bit count.
 constexpr uint32_t kFlagAgg = 1u << 30;
@@ -23,9 +23,9 @@ constexpr uint32_t kFlagPrefix = 2u << 30;
 constexpr uint32_t kCountMask = (1u << 30) - 1u;
 
 struct PassSched {
-    uint32_t skip;    // every key has the same pattern: the pass is the identity
-    uint32_t in_buf;  // 0: buffer A, 1: buffer B
-    uint32_t last;    // last executed pass: writes indices only
+    uint32_t skip;        // every element has the same digit: the pass is the identity
+    uint32_t in_buf;      // 0: buffer A, 1: buffer B
+    uint32_t write_keys;  // a later key pass still reads the keys
     uint32_t pad;
 };
 
@@ -34,7 +34,7 @@ struct Header {
     int32_t status;
     uint32_t final_buf;
     uint32_t nil_count;       // next[] entries equal to NIL
-    uint32_t pad0;
+    uint32_t expect_nil;      // many-list sorts: non-empty lists (one NIL each)
     uint64_t hsum[2];         // sum of h(next) over non-NIL next[] minus sum of h(i)
     PassSched sched[kMaxPasses];
 };
@@ -46,6 +46,7 @@ struct LevelPlan {
     size_t o_chain_rec;   // uint2 {successor chain, weight} per chain
     size_t o_ent;         // level 0: stored head entries of every chain
     size_t o_resume;      // level 0: node where the unstored rest of a chain starts
+    uint32_t cap;         // level 0: entries stored per chain
     size_t o_offn;        // u32 offset (in nodes) of every chain
 };
 
@@ -68,10 +69,14 @@ struct Plan {
     uint64_t n;
     uint32_t M, K, RB, radix, passes, flags, key_bytes;
     uint32_t tile, tiles, items;
+    uint32_t key_passes;  // passes on key patterns; the rest split on list ids
+    uint32_t num_lists;   // many-list sorts
+    uint32_t log_block;   // many-list sorts: node block size of the list table
     int levels;           // walk levels; the base ranks level `levels`
     LevelPlan lv[kMaxLevels];
     size_t o_header, o_hist, o_dbase, o_look, zero_end;
     size_t o_nodes, o_keysA, o_idxA, o_keysB, o_idxB;
+    size_t o_table, o_headbits;  // many-list sorts
     size_t total;
 };
 

@@ -1,0 +1,135 @@
+// Host-side launch helpers shared by the single-list and many-list paths.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "pbit_device.h"
+
+namespace pbit {
+
+static inline void mark(Prof* prof, hipStream_t s, int32_t stage)
+{
+    if (!prof || prof->count >= prof->n_events)
+        return;
+    hipEventRecord((hipEvent_t)prof->events[prof->count], s);
+    if (prof->ids)
+        prof->ids[prof->count] = stage;
+    prof->count++;
+}
+
+static inline hipError_t launch_zero(const Plan& P, char* ws, hipStream_t s)
+{
+    const size_t words = (P.zero_end - P.o_header) / 4;
+    const size_t want = (words + 255) / 256;
+    const uint32_t blocks = (uint32_t)(want < 4096 ? want : 4096);
+    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, (uint32_t*)(ws + P.o_header), words);
+    return hipGetLastError();
+}
+
+template <typename KeyT, int RB>
+static hipError_t launch_pack_rb(const Plan& P, const uint32_t* next, const void* keys, char* ws,
+                                 hipStream_t s)
+{
+    KeyT mask = 0;
+    if (P.flags & PBIT_SIGNED)
+        mask ^= (KeyT)((KeyT)1 << (sizeof(KeyT) * 8 - 1));
+    if (P.flags & PBIT_DESCENDING)
+        mask ^= (KeyT)~(KeyT)0;
+    const uint64_t want = (P.n + 255) / 256;
+    const uint32_t blocks = (uint32_t)(want < 1024 ? want : 1024);
+    const size_t shm = (size_t)P.key_passes * P.radix * sizeof(uint32_t);
+    hipLaunchKernelGGL((k_pack<KeyT, RB>), dim3(blocks), dim3(256), shm, s, next,
+                       (const KeyT*)keys, (uint32_t)P.n, mask, P.key_passes,
+                       (NodeRec<KeyT>*)(ws + P.o_nodes), (uint32_t*)(ws + P.o_hist),
+                       (Header*)(ws + P.o_header));
+    return hipGetLastError();
+}
+
+template <typename KeyT>
+static hipError_t launch_pack(const Plan& P, const uint32_t* next, const void* keys, char* ws,
+                              hipStream_t s)
+{
+    switch (P.RB) {
+    case 1: return launch_pack_rb<KeyT, 1>(P, next, keys, ws, s);
+    case 2: return launch_pack_rb<KeyT, 2>(P, next, keys, ws, s);
+    case 4: return launch_pack_rb<KeyT, 4>(P, next, keys, ws, s);
+    default: return launch_pack_rb<KeyT, 8>(P, next, keys, ws, s);
+    }
+}
+
+// Schedule, then P.key_passes passes on key patterns and the remaining
+// passes on list ids (many-list sorts).
+template <typename KeyT, int RB, typename LW>
+static hipError_t launch_passes_rb(const Plan& P, char* ws, hipStream_t s, Prof* prof,
+                                   const LidMap& lm)
+{
+    constexpr int BLOCK = kPassBlock;
+    constexpr int ITEMS = PassItems<KeyT>::value;
+    constexpr uint32_t RADIX = 1u << RB;
+    mark(prof, s, kStageSchedule);
+    hipLaunchKernelGGL((k_schedule<RB>), dim3(1), dim3(256), 0, s,
+                       (const uint32_t*)(ws + P.o_hist), (uint32_t*)(ws + P.o_dbase), P.passes,
+                       P.key_passes, (uint32_t)P.n, (Header*)(ws + P.o_header));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    for (uint32_t p = 0; p < P.passes; p++) {
+        LW* look = (LW*)(ws + P.o_look) + (size_t)p * P.tiles * RADIX;
+        const uint32_t* dbase = (const uint32_t*)(ws + P.o_dbase) + (size_t)p * RADIX;
+        mark(prof, s, kStagePass);
+        if (p < P.key_passes) {
+            hipLaunchKernelGGL((k_digit_pass<KeyT, RB, BLOCK, ITEMS, LW, false>), dim3(P.tiles),
+                               dim3(BLOCK), 0, s, p, p * RB, (uint32_t)P.n, (KeyT*)(ws + P.o_keysA),
+                               (uint32_t*)(ws + P.o_idxA), (KeyT*)(ws + P.o_keysB),
+                               (uint32_t*)(ws + P.o_idxB), dbase, look, (Header*)(ws + P.o_header),
+                               lm);
+        } else {
+            hipLaunchKernelGGL((k_digit_pass<KeyT, RB, BLOCK, ITEMS, LW, true>), dim3(P.tiles),
+                               dim3(BLOCK), 0, s, p, (p - P.key_passes) * RB, (uint32_t)P.n,
+                               (KeyT*)(ws + P.o_keysA), (uint32_t*)(ws + P.o_idxA),
+                               (KeyT*)(ws + P.o_keysB), (uint32_t*)(ws + P.o_idxB), dbase, look,
+                               (Header*)(ws + P.o_header), lm);
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+template <typename KeyT, typename LW>
+static hipError_t launch_passes(const Plan& P, char* ws, hipStream_t s, Prof* prof,
+                                const LidMap& lm)
+{
+    switch (P.RB) {
+    case 1: return launch_passes_rb<KeyT, 1, LW>(P, ws, s, prof, lm);
+    case 2: return launch_passes_rb<KeyT, 2, LW>(P, ws, s, prof, lm);
+    case 4: return launch_passes_rb<KeyT, 4, LW>(P, ws, s, prof, lm);
+    default: return launch_passes_rb<KeyT, 8, LW>(P, ws, s, prof, lm);
+    }
+}
+
+// Level-0 chains (lv[0]) to list order: stored entries, then re-walked rests.
+template <typename KeyT>
+static hipError_t launch_unchain(const Plan& P, char* ws, hipStream_t s, Prof* prof)
+{
+    const LevelPlan& L = P.lv[0];
+    const uint64_t threads = L.n_static * 16;
+    mark(prof, s, kStageUnchain);
+    hipLaunchKernelGGL((k_unchain<KeyT>), dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s,
+                       (const uint2*)(ws + L.o_chain_rec), (const Entry<KeyT>*)(ws + L.o_ent),
+                       (uint32_t)L.n_static, L.cap, (const uint32_t*)(ws + L.o_offn),
+                       (uint32_t)P.n, (KeyT*)(ws + P.o_keysA), (uint32_t*)(ws + P.o_idxA),
+                       (Header*)(ws + P.o_header));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    mark(prof, s, kStageWalk2);
+    hipLaunchKernelGGL((k_walk2<KeyT>), dim3((uint32_t)((L.n_static + 255) / 256)), dim3(256), 0, s,
+                       (const NodeRec<KeyT>*)(ws + P.o_nodes), (const uint2*)(ws + L.o_chain_rec),
+                       (const uint32_t*)(ws + L.o_resume), (uint32_t)L.n_static, L.cap,
+                       (const uint32_t*)(ws + L.o_offn), (uint32_t)P.n, (KeyT*)(ws + P.o_keysA),
+                       (uint32_t*)(ws + P.o_idxA), (Header*)(ws + P.o_header));
+    return hipGetLastError();
+}
+
+}  // namespace pbit

@@ -81,3 +81,56 @@ class ListSorter:
         if st != 0:
             raise PbitError(st)
         return h & 0xFFFFFFFF
+
+
+class ListsSorter:
+    """Sort many lists in one launch sequence (lists in contiguous node slabs).
+
+    heads: int32/uint32 tensor [L]; offsets: int64 tensor [L+1] of slab bounds;
+    next/keys: shared device arrays over all slabs.
+    """
+
+    def __init__(self, device="cuda"):
+        self.device = torch.device(device)
+        self._ws = None
+        self._ws_bytes = 0
+        self.status = torch.zeros(1, dtype=torch.int32, device=self.device)
+
+    def workspace(self, total: int, num_lists: int, M: int, K: int = 0) -> torch.Tensor:
+        need = _lib.lists_workspace_bytes(total, num_lists, M, K)
+        if need == 0:
+            raise PbitError(_lib.EINVAL)
+        if self._ws is None or self._ws_bytes < need:
+            self._ws = None
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+            self._ws_bytes = need
+        return self._ws
+
+    def sort_async(self, heads, offsets, next_in, keys, K: int = 0, descending: bool = False,
+                   signed: bool = False, next_out=None, new_heads=None, status=None,
+                   stream=None):
+        L = int(heads.numel())
+        total = int(next_in.numel())
+        M = key_bits(keys)
+        if next_out is None:
+            next_out = next_in
+        if new_heads is None:
+            new_heads = torch.empty(L, dtype=torch.int32, device=self.device)
+        if status is None:
+            status = self.status
+        ws = self.workspace(total, L, M, K)
+        flags = (_lib.DESCENDING if descending else 0) | (_lib.SIGNED if signed else 0)
+        st = _lib.sort_lists(heads, offsets, L, total, next_in, next_out, keys, M, K, flags,
+                             new_heads, status, ws, self._ws_bytes, stream)
+        if st != _lib.OK:
+            raise PbitError(st)
+        return new_heads, status
+
+    def sort(self, heads, offsets, next_in, keys, K: int = 0, descending: bool = False,
+             signed: bool = False, next_out=None):
+        new_heads, status = self.sort_async(heads, offsets, next_in, keys, K, descending, signed,
+                                            next_out)
+        st = int(status.item())
+        if st != 0:
+            raise PbitError(st)
+        return new_heads

@@ -88,3 +88,24 @@ def test_host_argument_checks(lib):
     assert lib.pbit_sort_list(9, 0x1000, 0x1000, 8, 32, 4) == E
     assert lib.pbit_sort_list(0, 0, 0x1000, 8, 32, 4) == E
     assert lib.pbit_sort_list(_lib.NIL, 0, 0, 0, 32, 4) == _lib.NIL
+
+
+def test_lists_host_checks(lib):
+    E = _lib.EINVAL
+    assert _lib.lists_workspace_bytes(1 << 20, 100, 32, 8) > 0
+    assert _lib.lists_workspace_bytes(1 << 20, 0, 32, 8) == 0
+    assert _lib.lists_workspace_bytes(1 << 20, 100, 32, 3) == 0
+    assert _lib.lists_workspace_bytes(0xFFFFFFFF, 100, 32, 8) == 0
+
+    def call(heads=0x1000, offs=0x2000, L=4, total=100, nin=0x3000, nout=0x3000, keys=0x4000,
+             M=32, K=8, flags=0, nh=0x5000, st=0x6000, ws=0x100000, wsb=1 << 40):
+        return lib.pbit_sort_lists(heads, offs, L, total, nin, nout, keys, M, K, flags, nh, st,
+                                   ws, wsb, None)
+    assert call(L=0) == E
+    assert call(M=24) == E
+    assert call(heads=0) == E
+    assert call(offs=0x2004) == E      # offsets must be 8-byte aligned
+    assert call(st=0) == E
+    assert call(nin=0) == E
+    assert call(flags=4) == E
+    assert call(wsb=100) == _lib.ENOMEM

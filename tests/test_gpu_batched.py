@@ -1,0 +1,156 @@
+"""GPU parity of the batched form: many lists in node slabs sorted in one
+launch sequence, bit-exact against the oracle's per-list sort and against the
+single-list entry point run on each list alone."""
+import numpy as np
+import pytest
+
+from paper_cs_0511020_amd import inputs
+
+from .gpu_util import NIL, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_cs_0511020_amd import _lib
+    _lib.load()
+
+
+def gpu_sort_lists(heads, offsets, nxt, keys, K, flags=0, inplace=False):
+    import torch
+    from paper_cs_0511020_amd.sorter import ListsSorter
+    s = ListsSorter()
+    ht = to_dev(heads.astype(np.uint32), torch)
+    ot = torch.from_numpy(np.asarray(offsets, dtype=np.int64)).to("cuda")
+    nt = to_dev(nxt.astype(np.uint32), torch)
+    kt = to_dev(keys, torch)
+    out = None if inplace else torch.full_like(nt, -1)
+    new_heads, status = s.sort_async(ht, ot, nt, kt, K, descending=bool(flags & 1),
+                                     signed=bool(flags & 2), next_out=out)
+    torch.cuda.synchronize()
+    st = int(status.item())
+    got = (nt if inplace else out).cpu().numpy().view(np.uint32)
+    return st, new_heads.cpu().numpy().view(np.uint32), got
+
+
+def oracle_lists(oracle_mod, heads, offsets, nxt, keys, K, flags=0):
+    M = keys.dtype.itemsize * 8
+    f = (oracle_mod.FLAG_DESCENDING if flags & 1 else 0) | (oracle_mod.FLAG_SIGNED if flags & 2 else 0)
+    st, out, nh = oracle_mod.sort_lists(heads, offsets, nxt, keys, M, K, flags=f)
+    assert st == 0
+    return nh, out
+
+
+def check(oracle_mod, heads, offsets, nxt, keys, K, flags=0, inplace=False):
+    st, nh, got = gpu_sort_lists(heads, offsets, nxt, keys, K, flags, inplace)
+    assert st == 0
+    enh, enext = oracle_lists(oracle_mod, heads, offsets, nxt, keys, K, flags)
+    assert np.array_equal(nh, enh)
+    assert np.array_equal(got, enext)
+
+
+def test_small_mixed_lengths(oracle_mod):
+    rng = inputs.rng_for(4101)
+    lengths = [0, 1, 2, 3, 15, 16, 17, 0, 31, 100, 1000, 4097, 1, 0, 20000]
+    nxt, heads, offs = inputs.slab_lists(lengths, rng)
+    keys = rng.integers(0, 50, size=nxt.shape[0]).astype(np.uint32)
+    for K in (4, 8):
+        say("small mixed K=%d" % K)
+        check(oracle_mod, heads, offs, nxt, keys, K)
+    check(oracle_mod, heads, offs, nxt, keys, 8, inplace=True)
+
+
+def test_single_list_batch_equals_plain(oracle_mod):
+    rng = inputs.rng_for(4102)
+    nxt, heads, offs = inputs.slab_lists([65536], rng)
+    keys = inputs.uniform_keys(65536, 32, rng)
+    check(oracle_mod, heads, offs, nxt, keys, 8)
+
+
+def test_c4_shape_reduced(oracle_mod):
+    """Log-uniform lengths like the 20 000-list batch, scaled down."""
+    rng = inputs.rng_for(4001)
+    lengths = inputs.log_uniform_lengths(1500, 4, 14, rng, 16, 1 << 14)
+    nxt, heads, offs = inputs.slab_lists(lengths, rng)
+    keys = inputs.uniform_keys(nxt.shape[0], 32, rng)
+    say("c4 reduced total=%d" % nxt.shape[0])
+    check(oracle_mod, heads, offs, nxt, keys, 8)
+
+
+@pytest.mark.parametrize("M,K", [(8, 4), (8, 8), (16, 4), (32, 4), (64, 8), (64, 4), (16, 2)])
+def test_key_widths(oracle_mod, M, K):
+    rng = inputs.rng_for(4200 + M + K)
+    lengths = inputs.log_uniform_lengths(200, 0, 12, rng, 0, 1 << 12)
+    nxt, heads, offs = inputs.slab_lists(lengths, rng)
+    keys = inputs.uniform_keys(nxt.shape[0], M, rng)
+    keys[::4] = keys[2]
+    say("batched M=%d K=%d" % (M, K))
+    check(oracle_mod, heads, offs, nxt, keys, K)
+    if M == 32:
+        check(oracle_mod, heads, offs, nxt, keys, K, flags=3)
+
+
+def test_many_lists_three_id_passes(oracle_mod):
+    """More than 2^16 lists: three 8-bit passes on the list id."""
+    rng = inputs.rng_for(4301)
+    lengths = rng.integers(0, 4, size=70000)
+    nxt, heads, offs = inputs.slab_lists(lengths, rng)
+    keys = rng.integers(0, 7, size=nxt.shape[0]).astype(np.uint16)
+    say("many lists total=%d" % nxt.shape[0])
+    check(oracle_mod, heads, offs, nxt, keys, 8)
+
+
+def test_batched_equals_alone():
+    """Each list of a batch sorts exactly as the single-list entry point
+    sorts it alone."""
+    import torch
+    from paper_cs_0511020_amd.sorter import ListSorter
+    from .gpu_util import gpu_sort
+    rng = inputs.rng_for(4401)
+    lengths = inputs.log_uniform_lengths(60, 4, 16, rng, 16, 1 << 16)
+    nxt, heads, offs = inputs.slab_lists(lengths, rng)
+    keys = rng.integers(0, 1 << 20, size=nxt.shape[0]).astype(np.uint32)
+    st, nh, got = gpu_sort_lists(heads, offs, nxt, keys, 8)
+    assert st == 0
+    sorter = ListSorter()
+    for l, ln in enumerate(lengths):
+        lo = int(offs[l])
+        local = np.where(nxt[lo:lo + ln] == NIL, NIL, nxt[lo:lo + ln] - lo).astype(np.uint32)
+        h, st1, g1 = gpu_sort(int(heads[l]) - lo, local, keys[lo:lo + ln], 8, sorter=sorter)
+        assert st1 == 0 and h + lo == nh[l]
+        exp = np.where(g1 == NIL, NIL, g1 + lo).astype(np.uint32)
+        assert np.array_equal(got[lo:lo + ln], exp)
+
+
+def test_batched_rejects_malformed():
+    rng = inputs.rng_for(4501)
+    lengths = [50, 70, 0, 40]
+    nxt, heads, offs = inputs.slab_lists(lengths, rng)
+    keys = rng.integers(0, 9, size=nxt.shape[0]).astype(np.uint32)
+    # swap two next pointers across slabs: every node keeps one predecessor
+    bad = nxt.copy()
+    a = int(heads[0]); b = int(heads[1])
+    bad[a], bad[b] = nxt[b], nxt[a]
+    st, nh, got = gpu_sort_lists(heads, offs, bad, keys, 8)
+    assert st == -2 and np.array_equal(got, np.full_like(bad, NIL))
+    # a cycle inside one slab
+    bad = nxt.copy()
+    tail = [i for i in range(50) if nxt[i] == NIL][0]
+    bad[tail] = heads[0]
+    st, _, _ = gpu_sort_lists(heads, offs, bad, keys, 8, inplace=True)
+    assert st == -2
+    # bad slab bounds or head
+    bad_offs = offs.copy(); bad_offs[2] = bad_offs[3] + 1
+    st, _, _ = gpu_sort_lists(heads, bad_offs, nxt, keys, 8)
+    assert st == -1
+    bad_heads = heads.copy(); bad_heads[2] = 5
+    st, _, _ = gpu_sort_lists(bad_heads, offs, nxt, keys, 8)
+    assert st == -1
