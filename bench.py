@@ -1,19 +1,25 @@
 #!/usr/bin/env python3
 """Benchmark of the MI355X Pbit list sort.
 
-One step = one whole sort (pack, list ranking, every digit pass, relink) of a
-single list of n = 2^24 nodes with uint32 keys and a random-permutation
-next[] layout, inputs resident in HBM.  The sort reads next_in and writes
-next_out (out of place, same traffic as in place), so every step sorts the
-same input.  Each kernel stage is bracketed by HIP events on the stream the
-library launches on; the dominant stage's algorithmic bytes per launch over
-its mean launch time give the roofline figure.
+Default run (the headline): one step = one whole sort (pack, list ranking,
+every digit pass, relink) of a single list of n = 2^24 nodes with uint32 keys
+and a random-permutation next[] layout, inputs resident in HBM.  The sort
+reads next_in and writes next_out (out of place, same traffic as in place),
+so every step sorts the same input.  Each kernel stage is bracketed by HIP
+events on the stream the library launches on; the dominant stage's
+algorithmic bytes per launch over its mean launch time give the roofline
+figure.
+
+The same JSON line carries a "batched" section: 20 000 lists with log-uniform
+lengths sorted by one batched call (direct and replayed from a HIP graph),
+against the same lists sorted by 20 000 single-list calls.
 
 Prints ONE JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -39,6 +45,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=1 << 24,
                     help="nodes in the list the CPU oracle sorts once")
+    ap.add_argument("--c4", default="secondary", choices=["none", "secondary", "full"],
+                    help="batched section: 20 000 lists up to 2^16 (secondary) or 2^20 (full)")
+    ap.add_argument("--batched-steps", type=int, default=5)
+    ap.add_argument("--no-plain-compare", action="store_true",
+                    help="skip the 20 000 single-list calls of the batched comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -67,46 +78,47 @@ def load_traffic(kernel: str, src_hash: str):
     return d.get("hbm_bytes_per_launch")
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the sort runs on a single "
-              "device; no multi-GPU path exists); run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
+def percentile(sorted_vals, q):
+    return sorted_vals[min(len(sorted_vals) - 1, int(round(q * (len(sorted_vals) - 1))))]
 
-    import ctypes
 
-    import numpy as np
-    import torch
+def stage_table(lib, pools, counts):
+    """Per-stage mean time per step and launches per step from event pools."""
+    names, per_stage, launches, lat = {}, {}, {}, []
+    for p, c in zip(pools, counts):
+        lat.append(p.elapsed_ms(0, c - 1))
+        tot, cnt = {}, {}
+        for i in range(c - 1):
+            sid = p.ids[i]
+            name = names.setdefault(sid, lib.pbit_stage_name(sid).decode())
+            tot[name] = tot.get(name, 0.0) + p.elapsed_ms(i, i + 1)
+            cnt[name] = cnt.get(name, 0) + 1
+        for name, v in tot.items():
+            per_stage.setdefault(name, []).append(v)
+            launches[name] = cnt[name]
+    return {k: statistics.mean(v) for k, v in per_stage.items()}, launches, sorted(lat)
 
-    from paper_cs_0511020_amd import _lib, bytemodel, inputs
-    from paper_cs_0511020_amd.hipevents import EventPool
 
-    if not torch.cuda.is_available():
-        print("bench.py: no GPU visible", file=sys.stderr)
-        sys.exit(1)
-    lib = _lib.load()
+def run_plain(args, lib, torch, np, inputs, bytemodel, EventPool):
     dev = torch.device("cuda:0")
     n, K, M = args.n, args.K, 32
     Keff = K if K else 8
     passes = M // Keff
     seed = {"uniform": 2001, "zipf": 2002, "distinct8": 2003}[args.dist]
-
     rng = inputs.rng_for(seed)
     nxt, head, order = inputs.random_list(n, rng)
     keys = inputs.c2_keys(args.dist, n, rng)
     next_in = torch.from_numpy(nxt.view(np.int32)).to(dev)
     keys_d = torch.from_numpy(keys.view(np.int32)).to(dev)
     next_out = torch.empty_like(next_in)
+    from paper_cs_0511020_amd import _lib
     ws_bytes = _lib.workspace_bytes(n, M, K)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     result = torch.zeros(2, dtype=torch.int32, device=dev)
-    stream = torch.cuda.current_stream()
-    sh = int(stream.cuda_stream)
-
+    sh = int(torch.cuda.current_stream().cuda_stream)
     max_ev = 64
     pools = [EventPool(max_ev) for _ in range(args.steps)]
-    warm_pool = EventPool(max_ev)
+    warm = EventPool(max_ev)
     rec = ctypes.c_int(0)
 
     def run(pool):
@@ -119,63 +131,36 @@ def main():
         return rec.value
 
     for _ in range(args.warmup):
-        run(warm_pool)
+        run(warm)
     torch.cuda.synchronize()
     h0, st0 = (int(x) & 0xFFFFFFFF for x in result.cpu().tolist())
     if st0 != 0:
         raise RuntimeError("device status %d" % st0)
-
     counts = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         counts.append(run(pools[k]))
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall_ms = (t1 - t0) * 1e3 / args.steps
+    wall_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    stage_ms, launches, lat = stage_table(lib, pools, counts)
+    p50, p99 = statistics.median(lat), percentile(lat, 0.99)
 
-    # per-step latency (first to last event) and per-stage times
-    stage_names = {}
-    per_stage = {}
-    launches = {}
-    lat = []
-    for k in range(args.steps):
-        p, c = pools[k], counts[k]
-        lat.append(p.elapsed_ms(0, c - 1))
-        step_tot, step_cnt = {}, {}
-        for i in range(c - 1):
-            sid = p.ids[i]
-            name = stage_names.setdefault(sid, lib.pbit_stage_name(sid).decode())
-            step_tot[name] = step_tot.get(name, 0.0) + p.elapsed_ms(i, i + 1)
-            step_cnt[name] = step_cnt.get(name, 0) + 1
-        for name, v in step_tot.items():
-            per_stage.setdefault(name, []).append(v)
-            launches[name] = step_cnt[name]
-    stage_ms = {k: statistics.mean(v) for k, v in per_stage.items()}
-    lat_sorted = sorted(lat)
-    p50 = statistics.median(lat_sorted)
-    p99 = lat_sorted[min(len(lat_sorted) - 1, int(round(0.99 * (len(lat_sorted) - 1))))]
-
-    # correctness of the timed configuration against the definition (cheap)
     got = next_out.cpu().numpy().view(np.uint32)
     exp_order = order[np.argsort(keys[order], kind="stable")]
     ok = (h0 == int(exp_order[0])) and bool(np.array_equal(got[exp_order[:-1]], exp_order[1:]))
 
     w = 4
-    executed_passes = launches.get("digit_pass", passes)
-    value = n / (wall_ms * 1e-3) / 1e6
-    path_bytes = bytemodel.path_bytes_per_node(w, passes) * n
-    path_frac = path_bytes / (p50 * 1e-3) / 1e9 / bytemodel.MI355X_HBM_PEAK_GBS
-
-    # dominant kernel: largest share of the step
-    roof_candidates = {k: v for k, v in stage_ms.items()
-                       if k in ("pack", "walk0", "unchain", "digit_pass", "relink")}
-    dom = max(roof_candidates, key=roof_candidates.get)
+    executed = launches.get("digit_pass", passes)
+    path_bpn = bytemodel.path_bytes_per_node(w, executed)
+    path_frac = path_bpn * n / (p50 * 1e-3) / 1e9 / bytemodel.MI355X_HBM_PEAK_GBS
+    cand = {k: v for k, v in stage_ms.items()
+            if k in ("pack", "walk0", "unchain", "digit_pass", "relink")}
+    dom = max(cand, key=cand.get)
     dom_launch_ms = stage_ms[dom] / launches[dom]
     if dom == "digit_pass":
-        # mean bytes per launch over the executed passes (the last writes no keys)
-        per_node = (bytemodel.kernel_bytes_per_node(dom, w) * (executed_passes - 1)
-                    + bytemodel.kernel_bytes_per_node(dom, w, last_pass=True)) / executed_passes
+        per_node = (bytemodel.kernel_bytes_per_node(dom, w) * (executed - 1)
+                    + bytemodel.kernel_bytes_per_node(dom, w, last_pass=True)) / executed
     else:
         per_node = bytemodel.kernel_bytes_per_node(dom, w)
     dom_bytes = per_node * n
@@ -189,9 +174,187 @@ def main():
         "algorithmic_bytes_per_launch": int(dom_bytes),
         "launch_ms": round(dom_launch_ms, 5),
     }
+    for p in pools + [warm]:
+        p.close()
+    del ws, next_in, next_out, keys_d
+    return {
+        "value": n / (wall_ms * 1e-3) / 1e6, "wall_ms": wall_ms, "p50": p50, "p99": p99,
+        "roofline": roofline, "stage_ms": stage_ms, "launches": launches, "correct": ok,
+        "path_bpn": path_bpn, "path_frac": path_frac, "Keff": Keff, "src_hash": src_hash,
+    }
+
+
+def run_batched(args, lib, torch, np, inputs, EventPool):
+    """20 000 lists, log-uniform lengths in [16, 2^hi]: one batched call vs
+    one single-list call per list, same inputs, same stream."""
+    from paper_cs_0511020_amd import _lib
+    dev = torch.device("cuda:0")
+    hi = 20 if args.c4 == "full" else 16
+    rng = inputs.rng_for(4001)
+    lengths = inputs.log_uniform_lengths(20000, 4, hi, rng, 16, 1 << hi)
+    compare = not args.no_plain_compare
+    d = inputs.slab_lists_device(lengths, seed=4001, M=32, local_copy=compare)
+    L = int(lengths.shape[0])
+    total = int(d["offsets_host"][-1])
+    M, K = 32, 8
+    ws_bytes = _lib.lists_workspace_bytes(total, L, M, K)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    next_out = torch.empty_like(d["next"])
+    new_heads = torch.empty(L, dtype=torch.int32, device=dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    sh = int(stream.cuda_stream)
+    max_ev = 96
+    steps = max(1, args.batched_steps)
+    pools = [EventPool(max_ev) for _ in range(steps)]
+    warm = EventPool(max_ev)
+    rec = ctypes.c_int(0)
+
+    def call_profiled(pool):
+        st = lib.pbit_sort_lists_profiled(
+            d["heads"].data_ptr(), d["offsets"].data_ptr(), L, total, d["next"].data_ptr(),
+            next_out.data_ptr(), d["keys"].data_ptr(), M, K, 0, new_heads.data_ptr(),
+            status.data_ptr(), ws.data_ptr(), ws_bytes, sh, pool.ptr(), pool.ids_ptr(), max_ev,
+            ctypes.byref(rec))
+        if st != 0:
+            raise RuntimeError("batched sort failed: " + _lib.status_string(st))
+        return rec.value
+
+    def call_plain_api():
+        st = lib.pbit_sort_lists(
+            d["heads"].data_ptr(), d["offsets"].data_ptr(), L, total, d["next"].data_ptr(),
+            next_out.data_ptr(), d["keys"].data_ptr(), M, K, 0, new_heads.data_ptr(),
+            status.data_ptr(), ws.data_ptr(), ws_bytes, sh)
+        if st != 0:
+            raise RuntimeError("batched sort failed: " + _lib.status_string(st))
+
+    call_profiled(warm)
+    torch.cuda.synchronize()
+    if int(status.item()) != 0:
+        raise RuntimeError("batched device status %d" % int(status.item()))
+    counts = []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        counts.append(call_profiled(pools[k]))
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3 / steps
+    stage_ms, launches, lat = stage_table(lib, pools, counts)
+
+    # the same call captured once in a HIP graph and replayed
+    graph_ms = None
+    graph_ok = None
+    try:
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g, stream=side):
+                st = lib.pbit_sort_lists(
+                    d["heads"].data_ptr(), d["offsets"].data_ptr(), L, total,
+                    d["next"].data_ptr(), next_out.data_ptr(), d["keys"].data_ptr(), M, K, 0,
+                    new_heads.data_ptr(), status.data_ptr(), ws.data_ptr(), ws_bytes,
+                    int(torch.cuda.current_stream().cuda_stream))
+        stream.wait_stream(side)
+        ref = next_out.clone()
+        g.replay()
+        torch.cuda.synchronize()
+        graph_ok = bool(torch.equal(next_out, ref)) and st == 0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.replay()
+        torch.cuda.synchronize()
+        graph_ms = (time.perf_counter() - t0) * 1e3 / steps
+        del g
+    except Exception as exc:  # graph capture is optional for the measurement
+        graph_ok = "unavailable: %s" % exc
+
+    out = {
+        "workload": "20000 lists, lengths log-uniform in [16, 2^%d], %d nodes, uint32 keys, "
+                    "random layout per slab, K=8" % (hi, total),
+        "lists": L, "nodes": total,
+        "batched_ms": round(wall_ms, 3),
+        "batched_Mnodes_s": round(total / (wall_ms * 1e-3) / 1e6, 1),
+        "batched_p50_ms": round(statistics.median(lat), 3),
+        "graph_replay_ms": None if graph_ms is None else round(graph_ms, 3),
+        "graph_replay_equal": graph_ok,
+        "stages_ms": {k: round(v, 3) for k, v in sorted(stage_ms.items(), key=lambda x: -x[1])},
+    }
+
+    if compare:
+        # single-list calls over the same lists (slab-local indices), one stream
+        maxlen = int(lengths.max())
+        pws_bytes = _lib.workspace_bytes(maxlen, M, K)
+        pws = torch.empty(pws_bytes, dtype=torch.uint8, device=dev)
+        pout = torch.empty_like(d["next_local"])
+        pres = torch.zeros(2 * L, dtype=torch.int32, device=dev)
+        offs = d["offsets_host"]
+        heads_h = d["heads_host"]
+        nl = d["next_local"].data_ptr()
+        po = pout.data_ptr()
+        kp = d["keys"].data_ptr()
+        rp = pres.data_ptr()
+        wp = pws.data_ptr()
+        fn = lib.pbit_sort_list_async
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for l in range(L):
+            lo = int(offs[l])
+            ln = int(offs[l + 1]) - lo
+            st = fn(int(heads_h[l]) - lo, nl + 4 * lo, po + 4 * lo, kp + 4 * lo, ln, M, K, 0,
+                    rp + 8 * l, wp, pws_bytes, sh)
+            if st != 0:
+                raise RuntimeError("plain call failed for list %d" % l)
+        torch.cuda.synchronize()
+        plain_ms = (time.perf_counter() - t0) * 1e3
+        # every list identical alone and in the batch
+        lens_t = torch.from_numpy(lengths).to(dev)
+        base = torch.repeat_interleave(d["offsets"][:-1], lens_t).to(torch.int32)
+        glob = torch.where(pout == -1, pout, pout + base)
+        same_next = bool(torch.equal(glob, next_out))
+        ph = pres.view(L, 2)
+        same_heads = bool(torch.equal(ph[:, 0] + d["offsets"][:-1].to(torch.int32), new_heads))
+        ok_status = bool(torch.all(ph[:, 1] == 0).item())
+        out.update({
+            "plain_calls_ms": round(plain_ms, 1),
+            "plain_Mnodes_s": round(total / (plain_ms * 1e-3) / 1e6, 1),
+            "speedup_batched_vs_plain": round(plain_ms / wall_ms, 2),
+            "identical_alone_and_batched": same_next and same_heads and ok_status,
+        })
+        del pws, pout, pres
+    for p in pools + [warm]:
+        p.close()
+    del ws, next_out, d
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (the sort runs on a single "
+              "device; no multi-GPU path exists); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_cs_0511020_amd import _lib, bytemodel, inputs
+    from paper_cs_0511020_amd.hipevents import EventPool
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    lib = _lib.load()
+
+    r = run_plain(args, lib, torch, np, inputs, bytemodel, EventPool)
+    torch.cuda.empty_cache()
+
+    batched = None
+    if args.c4 != "none":
+        batched = run_batched(args, lib, torch, np, inputs, EventPool)
 
     if args.copy_calibration:
-        a = torch.empty(1 << 28, dtype=torch.int32, device=dev)
+        a = torch.empty(1 << 28, dtype=torch.int32, device="cuda:0")
         b = torch.empty_like(a)
         for _ in range(3):
             b.copy_(a)
@@ -200,44 +363,45 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        cn = min(args.cpu_sample_n, n)
+        cn = min(args.cpu_sample_n, args.n)
+        seed = {"uniform": 2001, "zipf": 2002, "distinct8": 2003}[args.dist]
         crng = inputs.rng_for(seed + 100)
         cnxt, chead, _ = inputs.random_list(cn, crng)
         ckeys = inputs.c2_keys(args.dist, cn, crng)
         oracle.build(force=False)
         tc0 = time.perf_counter()
-        hh, _ = oracle.sort_list(chead, cnxt, ckeys, M, Keff)
+        oracle.sort_list(chead, cnxt, ckeys, 32, r["Keff"])
         tc1 = time.perf_counter()
         cpu = {"value": round(cn / (tc1 - tc0) / 1e6, 3), "unit": "Mnodes/s", "cores": 1,
                "kind": "oracle",
                "sample": "one sort of a %d-node list, same key distribution and layout recipe, "
-                         "K=%d, single-threaded C oracle, %.1f s" % (cn, Keff, tc1 - tc0)}
+                         "K=%d, single-threaded C oracle, %.1f s" % (cn, r["Keff"], tc1 - tc0)}
 
     out = {
         "metric": METRIC,
-        "value": round(value, 2),
+        "value": round(r["value"], 2),
         "unit": "Mnodes/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(wall_ms, 4),
+        "ms_per_step": round(r["wall_ms"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": "single list n=2^24 uint32 keys (%s), random-permutation next[] "
-                               "layout, K=%d, plain per-list launch" % (args.dist, Keff),
-                   "n": n, "M": M, "K": Keff, "dist": args.dist, "mode": "plain"},
-        "roofline": roofline,
+                               "layout, K=%d, plain per-list launch" % (args.dist, r["Keff"]),
+                   "n": args.n, "M": 32, "K": r["Keff"], "dist": args.dist, "mode": "plain"},
+        "roofline": r["roofline"],
         "cpu_baseline": cpu,
-        "latency_ms": {"p50": round(p50, 4), "p99": round(p99, 4)},
-        "path_roofline": {"bytes_per_node": bytemodel.path_bytes_per_node(w, passes),
-                          "frac_at_p50": round(path_frac, 4)},
-        "stages_ms": {k: round(v, 4) for k, v in sorted(stage_ms.items(), key=lambda x: -x[1])},
-        "stage_launches": launches,
-        "correct": ok,
-        "source_hash": src_hash,
+        "latency_ms": {"p50": round(r["p50"], 4), "p99": round(r["p99"], 4)},
+        "path_roofline": {"bytes_per_node": r["path_bpn"], "frac_at_p50": round(r["path_frac"], 4)},
+        "stages_ms": {k: round(v, 4) for k, v in sorted(r["stage_ms"].items(), key=lambda x: -x[1])},
+        "stage_launches": r["launches"],
+        "correct": r["correct"],
+        "batched": batched,
+        "source_hash": r["src_hash"],
     }
     print(json.dumps(out), flush=True)
 

@@ -121,3 +121,61 @@ def slab_lists(lengths, rng: np.random.Generator):
         nxt[order[-1]] = NIL
         heads[l] = order[0]
     return nxt, heads, offsets
+
+
+def slab_lists_device(lengths, seed: int, M: int = 32, device="cuda", local_copy: bool = False):
+    """The same recipe as ``slab_lists`` generated on the GPU with torch
+    (for batches too large to build on the host): each slab gets its own
+    uniformly random list order (torch.randperm) and a random head; keys are
+    uniform M-bit values.
+
+    Returns dict(next, heads, offsets, keys[, next_local]) of device tensors
+    (int32/int64 storage); ``next_local`` holds slab-local indices, for
+    sorting one list at a time with the single-list entry point.
+    """
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    lengths = np.asarray(lengths, dtype=np.int64)
+    offsets = np.zeros(lengths.shape[0] + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(lengths)
+    total = int(offsets[-1])
+    nxt = torch.full((total,), -1, dtype=torch.int32, device=device)
+    loc = torch.full((total,), -1, dtype=torch.int32, device=device) if local_copy else None
+    heads = np.full(lengths.shape[0], 0xFFFFFFFF, dtype=np.uint32)
+    for l, ln in enumerate(lengths):
+        ln = int(ln)
+        if ln == 0:
+            continue
+        lo = int(offsets[l])
+        perm = torch.randperm(ln, generator=g, device=device, dtype=torch.int64)
+        seg = nxt[lo:lo + ln]
+        seg[perm[:-1]] = (perm[1:] + lo).to(torch.int32)
+        if loc is not None:
+            lseg = loc[lo:lo + ln]
+            lseg[perm[:-1]] = perm[1:].to(torch.int32)
+        heads[l] = lo + int(perm[0].item())
+    if M == 8:
+        keys = torch.randint(0, 256, (total,), generator=g, device=device, dtype=torch.uint8)
+    elif M == 16:
+        keys = torch.randint(-(1 << 15), 1 << 15, (total,), generator=g, device=device,
+                             dtype=torch.int16)
+    elif M == 32:
+        keys = torch.randint(-(1 << 31), 1 << 31, (total,), generator=g, device=device,
+                             dtype=torch.int32)
+    else:
+        hi = torch.randint(-(1 << 31), 1 << 31, (total,), generator=g, device=device,
+                           dtype=torch.int64)
+        lo = torch.randint(0, 1 << 32, (total,), generator=g, device=device, dtype=torch.int64)
+        keys = (hi << 32) | lo
+    out = {
+        "next": nxt,
+        "heads": torch.from_numpy(heads.view(np.int32)).to(device),
+        "heads_host": heads,
+        "offsets": torch.from_numpy(offsets).to(device),
+        "offsets_host": offsets,
+        "keys": keys,
+    }
+    if loc is not None:
+        out["next_local"] = loc
+    return out
