@@ -160,11 +160,20 @@ __global__ __launch_bounds__(256) void k_walk_up(const uint2* __restrict__ recs,
         }
         start = (uint32_t)s;
     }
+    // A start element with no nodes is an empty chain of the level below (the
+    // chain slot of a start node that is the head): this chain is empty too.
+    // Only the head chain must not be empty.
+    if (recs[start].y == 0) {
+        if (c == 0)
+            set_error(&hdr->status, PBIT_EMALFORMED);
+        chain_rec[c] = make_uint2(kNil, 0);
+        return;
+    }
     const uint32_t lmask = (1u << log_l) - 1u;
     uint32_t cur = start, w = 0, steps = 0, nx;
     for (;;) {
         const uint2 r = recs[cur];
-        if (r.y == 0) {  // empty chain of the level below: not part of a list
+        if (r.y == 0) {  // an empty chain reached from a list: malformed
             set_error(&hdr->status, PBIT_EMALFORMED);
             nx = kNil;
             break;

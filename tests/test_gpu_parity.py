@@ -193,3 +193,20 @@ def test_c2_full_size_properties(oracle_mod, dist):
         assert st == 0
         out = check_properties(h, got, keys, order, oracle_mod.list_order)
         assert np.array_equal(out, definition_order(order, keys))
+
+
+@pytest.mark.parametrize("head", [0, 112, 16 * 15, 16 * 63, 16 * 8 * 8 * 8 - 16, 16 * 1023, 5])
+def test_head_on_chain_start_positions(oracle_mod, head):
+    """Heads whose index is a multiple of 16 leave the level-0 chain slot of
+    that node empty; when that slot is itself a chain start one or two levels
+    up it must read as an empty chain, not as a malformed list."""
+    say("head position %d" % head)
+    rng = inputs.rng_for(9100 + head)
+    n = 300007
+    order = rng.permutation(n).astype(np.uint32)
+    j = int(np.nonzero(order == head)[0][0])
+    order[[0, j]] = order[[j, 0]]
+    nxt, h = inputs.links_from_order(order)
+    assert h == head
+    keys = rng.integers(0, 1 << 16, size=n).astype(np.uint32)
+    run_parity(oracle_mod, head, nxt, keys, 8)
