@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--no-plain-compare", action="store_true",
                     help="skip the 20 000 single-list calls of the batched comparison")
+    ap.add_argument("--served", default="small", choices=["none", "small", "full"],
+                    help="served section: 300 requests up to 2^20 nodes (small) or 2000 up "
+                         "to 2^24 (full)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -328,6 +331,61 @@ def run_batched(args, lib, torch, np, inputs, EventPool):
     return out
 
 
+def run_served(args, torch, np, inputs):
+    """Poisson request stream, key widths {8,16,32,64}, lengths log-uniform:
+    saturated throughput X first (all requests at t = 0), then open loop at
+    0.7 X offered node rate with continuous batching, and the FIFO baseline
+    (one single-list call per request, one stream) at the same offered load."""
+    from paper_cs_0511020_amd.serve import (GpuExecutor, PlainExecutor, SortServer,
+                                            make_requests_device)
+    full = args.served == "full"
+    count, hi = (2000, 24) if full else (300, 20)
+    reqs = make_requests_device(count, seed=5001, lo_log2=10, hi_log2=hi)
+    torch.cuda.synchronize()
+    free = torch.cuda.mem_get_info()[0]
+    budget = int(free * 0.6)
+    mean_len = float(np.mean([r.n for r in reqs]))
+
+    def reset(arrivals):
+        for r, a in zip(reqs, arrivals):
+            r.arrival = float(a)
+            r.done = r.admitted = -1.0
+            r.batch = -1
+            r.new_head = -1
+
+    def summary(st):
+        d = st.as_dict()
+        return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()}
+
+    # warm the allocator and kernels once
+    SortServer(GpuExecutor(streams=2), slots=64, budget_bytes=budget).run(reqs[: min(40, count)])
+    reset(np.zeros(count))
+    sat = SortServer(GpuExecutor(streams=2), slots=64, budget_bytes=budget).run(reqs)
+    X = sat.throughput_mnodes_s * 1e6
+    rng = inputs.rng_for(5002)
+    lam = 0.7 * X / mean_len
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=count))
+    reset(arrivals)
+    opened = SortServer(GpuExecutor(streams=2), slots=64, budget_bytes=budget).run(reqs)
+    ok = all(r.status == 0 for r in reqs)
+    reset(arrivals)
+    fifo = SortServer(PlainExecutor(), slots=1, budget_bytes=budget).run(reqs)
+    out = {
+        "workload": "%d requests, lengths log-uniform in [2^10, 2^%d], key widths uniform over "
+                    "{8,16,32,64}, uniform keys, device-resident, Poisson arrivals at 0.7 of the "
+                    "saturated rate" % (count, hi),
+        "nodes": int(sum(r.n for r in reqs)),
+        "saturated": summary(sat),
+        "offered_mnodes_s": round(0.7 * X / 1e6, 1),
+        "batched_open_loop": summary(opened),
+        "fifo_plain_open_loop": summary(fifo),
+        "all_ok": ok,
+    }
+    del reqs
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -352,6 +410,9 @@ def main():
     batched = None
     if args.c4 != "none":
         batched = run_batched(args, lib, torch, np, inputs, EventPool)
+    served = None
+    if args.served != "none":
+        served = run_served(args, torch, np, inputs)
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.int32, device="cuda:0")
@@ -401,6 +462,7 @@ def main():
         "stage_launches": r["launches"],
         "correct": r["correct"],
         "batched": batched,
+        "served": served,
         "source_hash": r["src_hash"],
     }
     print(json.dumps(out), flush=True)

@@ -147,6 +147,27 @@ int pbit_sort_lists(const uint32_t *d_heads, const uint64_t *d_offsets, uint32_t
                     uint32_t *d_new_heads, int32_t *d_status, void *ws, size_t ws_bytes,
                     void *stream);
 
+/*
+ * Gather form of pbit_sort_lists for lists that live in separate arrays (a
+ * request server batching independent requests without copying them).  List
+ * l has len_l = d_offsets[l+1] - d_offsets[l] nodes; its arrays are given by
+ * device pointers stored in device memory:
+ *   d_next_in_ptrs[l]   uint32[len_l] next[] in LIST-LOCAL indices
+ *                       (0..len_l-1, PBIT_NIL at the end)
+ *   d_key_ptrs[l]       keys of M bits, len_l entries
+ *   d_next_out_ptrs[l]  uint32[len_l] receives the relinked next[] (local
+ *                       indices; may equal d_next_in_ptrs[l])
+ * d_heads[l] and d_new_heads[l] are list-local too.  d_offsets only sets the
+ * lists' places in the workspace.  Results, errors and workspace size are
+ * those of pbit_sort_lists with the same offsets.
+ */
+int pbit_sort_lists_gather(const uint32_t *d_heads, const uint64_t *d_offsets,
+                           uint32_t num_lists, uint64_t total_nodes,
+                           const uint64_t *d_next_in_ptrs, const uint64_t *d_next_out_ptrs,
+                           const uint64_t *d_key_ptrs, uint32_t M, uint32_t K, uint32_t flags,
+                           uint32_t *d_new_heads, int32_t *d_status, void *ws, size_t ws_bytes,
+                           void *stream);
+
 /* Measurement form of pbit_sort_lists (see pbit_sort_list_profiled). */
 int pbit_sort_lists_profiled(const uint32_t *d_heads, const uint64_t *d_offsets,
                              uint32_t num_lists, uint64_t total_nodes, const uint32_t *next_in,

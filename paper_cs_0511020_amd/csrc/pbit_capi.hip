@@ -16,8 +16,9 @@ hipError_t enqueue_sort(const Plan& P, uint32_t head, const uint32_t* next_in, u
 hipError_t enqueue_empty(uint32_t* d_result, hipStream_t s);
 hipError_t enqueue_sort_lists(const Plan& P, const uint32_t* heads, const uint64_t* offsets,
                               const uint32_t* next_in, uint32_t* next_out, const void* keys,
-                              uint32_t* new_heads, int32_t* d_status, char* ws, hipStream_t s,
-                              Prof* prof);
+                              const uint64_t* next_in_ptrs, const uint64_t* next_out_ptrs,
+                              const uint64_t* key_ptrs, uint32_t* new_heads, int32_t* d_status,
+                              char* ws, hipStream_t s, Prof* prof);
 uint32_t pass_tile(uint32_t key_bytes);
 
 static size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
@@ -351,8 +352,36 @@ static int sort_lists_impl(const uint32_t* d_heads, const uint64_t* d_offsets, u
         return PBIT_EINVAL;
     if (ws_bytes < P.total)
         return PBIT_ENOMEM;
-    hipError_t e = enqueue_sort_lists(P, d_heads, d_offsets, next_in, next_out, keys, d_new_heads,
-                                      d_status, (char*)ws, (hipStream_t)stream, prof);
+    hipError_t e = enqueue_sort_lists(P, d_heads, d_offsets, next_in, next_out, keys, nullptr,
+                                      nullptr, nullptr, d_new_heads, d_status, (char*)ws,
+                                      (hipStream_t)stream, prof);
+    return e == hipSuccess ? PBIT_OK : PBIT_EHIP;
+}
+
+extern "C" int pbit_sort_lists_gather(const uint32_t* d_heads, const uint64_t* d_offsets,
+                                      uint32_t num_lists, uint64_t total_nodes,
+                                      const uint64_t* d_next_in_ptrs,
+                                      const uint64_t* d_next_out_ptrs,
+                                      const uint64_t* d_key_ptrs, uint32_t M, uint32_t K,
+                                      uint32_t flags, uint32_t* d_new_heads, int32_t* d_status,
+                                      void* ws, size_t ws_bytes, void* stream)
+{
+    Plan P;
+    if (!make_plan_lists(total_nodes, num_lists, M, K, flags, &P))
+        return PBIT_EINVAL;
+    if (!d_heads || !d_offsets || !d_new_heads || !d_status || !ws || !d_next_in_ptrs ||
+        !d_next_out_ptrs || !d_key_ptrs)
+        return PBIT_EINVAL;
+    if (((uintptr_t)d_heads & 3u) || ((uintptr_t)d_offsets & 7u) || ((uintptr_t)d_new_heads & 3u) ||
+        ((uintptr_t)d_status & 3u) || ((uintptr_t)d_next_in_ptrs & 7u) ||
+        ((uintptr_t)d_next_out_ptrs & 7u) || ((uintptr_t)d_key_ptrs & 7u) ||
+        ((uintptr_t)ws & 255u))
+        return PBIT_EINVAL;
+    if (ws_bytes < P.total)
+        return PBIT_ENOMEM;
+    hipError_t e = enqueue_sort_lists(P, d_heads, d_offsets, nullptr, nullptr, nullptr,
+                                      d_next_in_ptrs, d_next_out_ptrs, d_key_ptrs, d_new_heads,
+                                      d_status, (char*)ws, (hipStream_t)stream, nullptr);
     return e == hipSuccess ? PBIT_OK : PBIT_EHIP;
 }
 

@@ -77,12 +77,66 @@ constexpr uint64_t kHashK1 = 0x9E3779B97F4A7C15ull;
 constexpr uint64_t kHashK2 = 0xD6E8FEB86659FD93ull;
 
 // ---------------------------------------------------------------- pack
+// Where pack reads node i: one pair of next[]/keys[] arrays over all nodes...
+template <typename KeyT> struct DirectSrc {
+    const uint32_t* next;
+    const KeyT* keys;
+    __device__ __forceinline__ void load(size_t i, uint32_t n, uint32_t& nx, KeyT& k,
+                                         bool& bad) const
+    {
+        nx = next[i];
+        k = keys[i];
+        bad |= (nx != kNil) && (nx >= n);
+    }
+};
+
+// Node -> list of a many-list sort: lists own contiguous node ranges
+// [offsets[l], offsets[l+1]); table[b] is the list holding node b << log_block.
+struct LidMap {
+    const uint32_t* table;
+    const uint64_t* offsets;
+    uint32_t num_lists;
+    uint32_t log_block;
+};
+
+__device__ __forceinline__ uint32_t list_of(const LidMap& lm, uint32_t node)
+{
+    uint32_t l = min(lm.table[node >> lm.log_block], lm.num_lists - 1u);
+    while (l + 1 < lm.num_lists && lm.offsets[l + 1] <= node)
+        l++;
+    return l;
+}
+
+// ... or one array pair per list (device pointers), holding list-local node
+// indices; node i of the batch is node i - offsets[l] of list l.
+template <typename KeyT> struct GatherSrc {
+    LidMap lm;
+    const uint64_t* next_ptrs;
+    const uint64_t* key_ptrs;
+    __device__ __forceinline__ void load(size_t i, uint32_t, uint32_t& nx, KeyT& k,
+                                         bool& bad) const
+    {
+        const uint32_t l = list_of(lm, (uint32_t)i);
+        const uint64_t off = lm.offsets[l];
+        const uint64_t len = lm.offsets[l + 1] - off;
+        const uint64_t loc = i - off;
+        const uint32_t nl = ((const uint32_t*)next_ptrs[l])[loc];
+        k = ((const KeyT*)key_ptrs[l])[loc];
+        if (nl == kNil) {
+            nx = kNil;
+        } else if (nl < len) {
+            nx = (uint32_t)(nl + off);
+        } else {
+            nx = kNil;
+            bad = true;
+        }
+    }
+};
+
 // Node records, the count of every pattern value of every key pass, the NIL
 // count and the hash sums sum h(next) - sum h(i).
-template <typename KeyT, int RB>
-__global__ __launch_bounds__(256) void k_pack(const uint32_t* __restrict__ next,
-                                              const KeyT* __restrict__ keys, uint32_t n,
-                                              KeyT xor_mask, uint32_t passes,
+template <typename KeyT, int RB, class Src>
+__global__ __launch_bounds__(256) void k_pack(Src src, uint32_t n, KeyT xor_mask, uint32_t passes,
                                               NodeRec<KeyT>* __restrict__ nodes,
                                               uint32_t* __restrict__ hist, Header* hdr)
 {
@@ -97,9 +151,10 @@ __global__ __launch_bounds__(256) void k_pack(const uint32_t* __restrict__ next,
     uint32_t nils = 0;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += stride) {
-        const uint32_t nx = next[i];
-        const KeyT k = keys[i] ^ xor_mask;
-        bad |= (nx != kNil) && (nx >= n);
+        uint32_t nx;
+        KeyT k;
+        src.load(i, n, nx, k, bad);
+        k ^= xor_mask;
         if (nx == kNil) {
             nils++;
         } else {
@@ -296,23 +351,6 @@ template <> struct Look<uint32_t> {
 template <> struct Look<uint64_t> {
     static constexpr uint64_t AGG = 1ull << 32, PREFIX = 2ull << 32, MASK = 0xFFFFFFFFull;
 };
-
-// Node -> list of a many-list sort: lists own contiguous node slabs
-// [offsets[l], offsets[l+1]); table[b] is the list holding node b << log_block.
-struct LidMap {
-    const uint32_t* table;
-    const uint64_t* offsets;
-    uint32_t num_lists;
-    uint32_t log_block;
-};
-
-__device__ __forceinline__ uint32_t list_of(const LidMap& lm, uint32_t node)
-{
-    uint32_t l = min(lm.table[node >> lm.log_block], lm.num_lists - 1u);
-    while (l + 1 < lm.num_lists && lm.offsets[l + 1] <= node)
-        l++;
-    return l;
-}
 
 template <typename SKey> struct KV { SKey key; uint32_t idx; };
 

@@ -24,7 +24,20 @@ struct ForestArgs {
     uint32_t n;
     LidMap lm;
     const uint32_t* head_bits;
+    // gather form: per-list arrays with list-local indices (null otherwise)
+    const uint64_t* next_in_ptrs;
+    const uint64_t* next_out_ptrs;
+    const uint64_t* key_ptrs;
 };
+
+// Head of list l as a batch node index (gather form: the head is list-local).
+__device__ __forceinline__ uint32_t head_of(const ForestArgs& F, uint32_t l, uint64_t lo)
+{
+    const uint32_t h = F.heads[l];
+    if (!F.next_in_ptrs || h == kNil)
+        return h;
+    return (uint32_t)min<uint64_t>(lo + h, (uint64_t)kNil);
+}
 
 __device__ __forceinline__ bool is_head(const ForestArgs& F, uint32_t node)
 {
@@ -43,7 +56,7 @@ __global__ __launch_bounds__(256) void k_fprep(ForestArgs F, uint32_t* __restric
     if (l >= F.H)
         return;
     const uint64_t lo = F.offsets[l], hi = F.offsets[l + 1];
-    const uint32_t head = F.heads[l];
+    const uint32_t head = hi >= lo ? head_of(F, l, lo) : kNil;
     bool ok = hi >= lo && hi <= F.n && (l != 0 || lo == 0) && (l + 1 != F.H || hi == F.n);
     if (ok && hi == lo)
         ok = head == kNil;
@@ -104,7 +117,7 @@ __global__ __launch_bounds__(256) void k_fwalk0(const NodeRec<KeyT>* __restrict_
             chain_rec[c] = make_uint2(kNil, 0);
             return;
         }
-        start = F.heads[c];
+        start = head_of(F, c, lo);
     } else {
         const uint64_t j = (uint64_t)(c - F.H) << kLog0;
         if (j >= n || is_head(F, (uint32_t)j)) {
@@ -277,7 +290,8 @@ __global__ __launch_bounds__(256) void k_fdown(const uint2* __restrict__ recs, u
 }
 
 // next_out[order[j]] = order[j+1] inside each list's run, NIL at its end;
-// the first node of each run is the list's new head.
+// the first node of each run is the list's new head.  In the gather form the
+// result goes to each list's own array in list-local indices.
 __global__ __launch_bounds__(256) void k_frelink(const uint32_t* __restrict__ idxA,
                                                  const uint32_t* __restrict__ idxB, ForestArgs F,
                                                  uint32_t* __restrict__ next_out,
@@ -299,10 +313,18 @@ __global__ __launch_bounds__(256) void k_frelink(const uint32_t* __restrict__ id
     const uint64_t lo = F.offsets[l], hi = F.offsets[l + 1];
     const uint32_t node = order[j];
     const uint32_t succ = (j + 1 < hi) ? order[j + 1] : kNil;
-    if (node < F.n)
+    if (node < lo || node >= hi)
+        return;  // cannot happen for a sorted batch; keeps every write in bounds
+    if (F.next_out_ptrs) {
+        uint32_t* out = (uint32_t*)F.next_out_ptrs[l];
+        out[node - lo] = succ == kNil ? kNil : (uint32_t)(succ - lo);
+        if (j == lo)
+            new_heads[l] = (uint32_t)(node - lo);
+    } else {
         next_out[node] = succ;
-    if (j == lo)
-        new_heads[l] = node;
+        if (j == lo)
+            new_heads[l] = node;
+    }
 }
 
 __global__ void k_fempty(uint32_t* __restrict__ new_heads, uint32_t H, int32_t* d_status)
@@ -328,8 +350,9 @@ static hipError_t launch_fwalk0(const Plan& P, const ForestArgs& F, char* ws, hi
 
 hipError_t enqueue_sort_lists(const Plan& P, const uint32_t* heads, const uint64_t* offsets,
                               const uint32_t* next_in, uint32_t* next_out, const void* keys,
-                              uint32_t* new_heads, int32_t* d_status, char* ws, hipStream_t s,
-                              Prof* prof)
+                              const uint64_t* next_in_ptrs, const uint64_t* next_out_ptrs,
+                              const uint64_t* key_ptrs, uint32_t* new_heads, int32_t* d_status,
+                              char* ws, hipStream_t s, Prof* prof)
 {
     hipError_t e;
     Header* hdr = (Header*)(ws + P.o_header);
@@ -348,6 +371,9 @@ hipError_t enqueue_sort_lists(const Plan& P, const uint32_t* heads, const uint64
     F.lm.num_lists = P.num_lists;
     F.lm.log_block = P.log_block;
     F.head_bits = (const uint32_t*)(ws + P.o_headbits);
+    F.next_in_ptrs = next_in_ptrs;
+    F.next_out_ptrs = next_out_ptrs;
+    F.key_ptrs = key_ptrs;
 
     mark(prof, s, kStageZero);
     if ((e = launch_zero(P, ws, s)) != hipSuccess)
@@ -367,11 +393,20 @@ hipError_t enqueue_sort_lists(const Plan& P, const uint32_t* heads, const uint64
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
     mark(prof, s, kStagePack);
-    switch (P.key_bytes) {
-    case 1: e = launch_pack<uint8_t>(P, next_in, keys, ws, s); break;
-    case 2: e = launch_pack<uint16_t>(P, next_in, keys, ws, s); break;
-    case 4: e = launch_pack<uint32_t>(P, next_in, keys, ws, s); break;
-    default: e = launch_pack<uint64_t>(P, next_in, keys, ws, s); break;
+    if (next_in_ptrs) {
+        switch (P.key_bytes) {
+        case 1: e = launch_pack_src<uint8_t>(P, GatherSrc<uint8_t>{F.lm, next_in_ptrs, key_ptrs}, ws, s); break;
+        case 2: e = launch_pack_src<uint16_t>(P, GatherSrc<uint16_t>{F.lm, next_in_ptrs, key_ptrs}, ws, s); break;
+        case 4: e = launch_pack_src<uint32_t>(P, GatherSrc<uint32_t>{F.lm, next_in_ptrs, key_ptrs}, ws, s); break;
+        default: e = launch_pack_src<uint64_t>(P, GatherSrc<uint64_t>{F.lm, next_in_ptrs, key_ptrs}, ws, s); break;
+        }
+    } else {
+        switch (P.key_bytes) {
+        case 1: e = launch_pack<uint8_t>(P, next_in, keys, ws, s); break;
+        case 2: e = launch_pack<uint16_t>(P, next_in, keys, ws, s); break;
+        case 4: e = launch_pack<uint32_t>(P, next_in, keys, ws, s); break;
+        default: e = launch_pack<uint64_t>(P, next_in, keys, ws, s); break;
+        }
     }
     if (e != hipSuccess)
         return e;

@@ -25,9 +25,8 @@ static inline hipError_t launch_zero(const Plan& P, char* ws, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename KeyT, int RB>
-static hipError_t launch_pack_rb(const Plan& P, const uint32_t* next, const void* keys, char* ws,
-                                 hipStream_t s)
+template <typename KeyT, int RB, class Src>
+static hipError_t launch_pack_rb(const Plan& P, const Src& src, char* ws, hipStream_t s)
 {
     KeyT mask = 0;
     if (P.flags & PBIT_SIGNED)
@@ -37,23 +36,28 @@ static hipError_t launch_pack_rb(const Plan& P, const uint32_t* next, const void
     const uint64_t want = (P.n + 255) / 256;
     const uint32_t blocks = (uint32_t)(want < 1024 ? want : 1024);
     const size_t shm = (size_t)P.key_passes * P.radix * sizeof(uint32_t);
-    hipLaunchKernelGGL((k_pack<KeyT, RB>), dim3(blocks), dim3(256), shm, s, next,
-                       (const KeyT*)keys, (uint32_t)P.n, mask, P.key_passes,
-                       (NodeRec<KeyT>*)(ws + P.o_nodes), (uint32_t*)(ws + P.o_hist),
-                       (Header*)(ws + P.o_header));
+    hipLaunchKernelGGL((k_pack<KeyT, RB, Src>), dim3(blocks), dim3(256), shm, s, src,
+                       (uint32_t)P.n, mask, P.key_passes, (NodeRec<KeyT>*)(ws + P.o_nodes),
+                       (uint32_t*)(ws + P.o_hist), (Header*)(ws + P.o_header));
     return hipGetLastError();
+}
+
+template <typename KeyT, class Src>
+static hipError_t launch_pack_src(const Plan& P, const Src& src, char* ws, hipStream_t s)
+{
+    switch (P.RB) {
+    case 1: return launch_pack_rb<KeyT, 1>(P, src, ws, s);
+    case 2: return launch_pack_rb<KeyT, 2>(P, src, ws, s);
+    case 4: return launch_pack_rb<KeyT, 4>(P, src, ws, s);
+    default: return launch_pack_rb<KeyT, 8>(P, src, ws, s);
+    }
 }
 
 template <typename KeyT>
 static hipError_t launch_pack(const Plan& P, const uint32_t* next, const void* keys, char* ws,
                               hipStream_t s)
 {
-    switch (P.RB) {
-    case 1: return launch_pack_rb<KeyT, 1>(P, next, keys, ws, s);
-    case 2: return launch_pack_rb<KeyT, 2>(P, next, keys, ws, s);
-    case 4: return launch_pack_rb<KeyT, 4>(P, next, keys, ws, s);
-    default: return launch_pack_rb<KeyT, 8>(P, next, keys, ws, s);
-    }
+    return launch_pack_src<KeyT>(P, DirectSrc<KeyT>{next, (const KeyT*)keys}, ws, s);
 }
 
 // Schedule, then P.key_passes passes on key patterns and the remaining
