@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=1 << 24)
     ap.add_argument("--K", type=int, default=8, help="pattern bits (4 or 8; 0 = library choice)")
+    ap.add_argument("--M", type=int, default=32, choices=[32, 64], help="key bits")
     ap.add_argument("--dist", default="uniform", choices=["uniform", "zipf", "distinct8"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=1 << 24,
@@ -68,15 +69,15 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str, src_hash: str):
+def load_traffic(kernel: str, src_hash: str, config: dict):
     """HBM bytes per launch from committed rocprofv3 counter summaries, if they
-    were taken on the current kernel sources."""
+    were taken on the current kernel sources and the same workload."""
     path = os.path.join(ROOT, "profiles", "traffic_%s.json" % kernel)
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("source_hash") != src_hash:
+    if d.get("source_hash") != src_hash or d.get("config") != config:
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -104,15 +105,19 @@ def stage_table(lib, pools, counts):
 
 def run_plain(args, lib, torch, np, inputs, bytemodel, EventPool):
     dev = torch.device("cuda:0")
-    n, K, M = args.n, args.K, 32
+    n, K, M = args.n, args.K, args.M
     Keff = K if K else 8
     passes = M // Keff
     seed = {"uniform": 2001, "zipf": 2002, "distinct8": 2003}[args.dist]
     rng = inputs.rng_for(seed)
     nxt, head, order = inputs.random_list(n, rng)
-    keys = inputs.c2_keys(args.dist, n, rng)
+    if M == 64:
+        keys = inputs.uniform_keys(n, 64, rng)
+        keys_d = torch.from_numpy(keys.view(np.int64)).to(dev)
+    else:
+        keys = inputs.c2_keys(args.dist, n, rng)
+        keys_d = torch.from_numpy(keys.view(np.int32)).to(dev)
     next_in = torch.from_numpy(nxt.view(np.int32)).to(dev)
-    keys_d = torch.from_numpy(keys.view(np.int32)).to(dev)
     next_out = torch.empty_like(next_in)
     from paper_cs_0511020_amd import _lib
     ws_bytes = _lib.workspace_bytes(n, M, K)
@@ -153,7 +158,7 @@ def run_plain(args, lib, torch, np, inputs, bytemodel, EventPool):
     exp_order = order[np.argsort(keys[order], kind="stable")]
     ok = (h0 == int(exp_order[0])) and bool(np.array_equal(got[exp_order[:-1]], exp_order[1:]))
 
-    w = 4
+    w = M // 8
     executed = launches.get("digit_pass", passes)
     path_bpn = bytemodel.path_bytes_per_node(w, executed)
     path_frac = path_bpn * n / (p50 * 1e-3) / 1e9 / bytemodel.MI355X_HBM_PEAK_GBS
@@ -173,7 +178,7 @@ def run_plain(args, lib, torch, np, inputs, bytemodel, EventPool):
         "bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
         "peak": bytemodel.MI355X_HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / bytemodel.MI355X_HBM_PEAK_GBS, 4),
-        "traffic": load_traffic(dom, src_hash),
+        "traffic": load_traffic(dom, src_hash, {"n": n, "M": M, "K": Keff, "dist": args.dist}),
         "algorithmic_bytes_per_launch": int(dom_bytes),
         "launch_ms": round(dom_launch_ms, 5),
     }
@@ -431,7 +436,9 @@ def main():
         ckeys = inputs.c2_keys(args.dist, cn, crng)
         oracle.build(force=False)
         tc0 = time.perf_counter()
-        oracle.sort_list(chead, cnxt, ckeys, 32, r["Keff"])
+        if args.M == 64:
+            ckeys = inputs.uniform_keys(cn, 64, crng)
+        oracle.sort_list(chead, cnxt, ckeys, args.M, r["Keff"])
         tc1 = time.perf_counter()
         cpu = {"value": round(cn / (tc1 - tc0) / 1e6, 3), "unit": "Mnodes/s", "cores": 1,
                "kind": "oracle",
@@ -449,11 +456,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32",
+        "dtype": "u%d" % args.M,
         "data": "synthetic",
-        "config": {"workload": "single list n=2^24 uint32 keys (%s), random-permutation next[] "
-                               "layout, K=%d, plain per-list launch" % (args.dist, r["Keff"]),
-                   "n": args.n, "M": 32, "K": r["Keff"], "dist": args.dist, "mode": "plain"},
+        "config": {"workload": "single list n=%d uint%d keys (%s), random-permutation next[] "
+                               "layout, K=%d, plain per-list launch"
+                               % (args.n, args.M, args.dist if args.M == 32 else "uniform",
+                                  r["Keff"]),
+                   "n": args.n, "M": args.M, "K": r["Keff"], "dist": args.dist, "mode": "plain"},
         "roofline": r["roofline"],
         "cpu_baseline": cpu,
         "latency_ms": {"p50": round(r["p50"], 4), "p99": round(r["p99"], 4)},

@@ -210,3 +210,24 @@ def test_head_on_chain_start_positions(oracle_mod, head):
     assert h == head
     keys = rng.integers(0, 1 << 16, size=n).astype(np.uint32)
     run_parity(oracle_mod, head, nxt, keys, 8)
+
+
+@pytest.mark.parametrize("K", [8, 4])
+def test_c3_u64_with_payload_full_size(oracle_mod, K):
+    """n = 2^26 nodes, uint64 keys, a uint64 payload per node: nodes never
+    move, so walking the result must give the definition's (key, payload)
+    sequence; checked by the properties that fix the stable sort and by
+    numpy's stable argsort."""
+    say("C3 full K=%d" % K)
+    rng = inputs.rng_for(3001)
+    n = 1 << 26
+    nxt, head, order = inputs.random_list(n, rng)
+    keys = inputs.uniform_keys(n, 64, rng)
+    payload = inputs.uniform_keys(n, 64, rng)
+    h, st, got = gpu_sort(head, nxt, keys, K, inplace=False)
+    assert st == 0
+    out = check_properties(h, got, keys, order, oracle_mod.list_order)
+    exp = definition_order(order, keys)
+    assert np.array_equal(out, exp)
+    assert np.array_equal(payload[out], payload[exp])
+    del nxt, keys, payload, got
