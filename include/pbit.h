@@ -20,14 +20,20 @@
  *   head     index of the first node (Sec. 1, the root), PBIT_NIL if empty.
  * Nodes never move: a payload attached to a node travels with its index.
  *
- * Flags (Sec. 6 and Sec. 7-8): PBIT_DESCENDING gives the largest key first,
- * PBIT_SIGNED reads keys as two's-complement integers.  Equal keys keep list
- * order in every mode.
+ * Flags (Sec. 6, Sec. 7-8 and Sec. 14): PBIT_DESCENDING gives the largest
+ * key first, PBIT_SIGNED reads keys as two's-complement integers, PBIT_FLOAT
+ * reads them as IEEE-754 sign-magnitude numbers of width M (binary16 or
+ * bfloat16, binary32, binary64; any 8-bit sign-magnitude format too).
+ * Floating-point order is numeric, with -0 before +0 and NaNs outside the
+ * infinities on the side of their sign bit (the total order of IEEE-754
+ * 2008, Sec. 5.10).  PBIT_SIGNED and PBIT_FLOAT together are PBIT_EINVAL.
+ * Equal keys (equal bit patterns) keep list order in every mode.
  *
  * Errors are negative return values:
  *   PBIT_EINVAL     bad argument found on the host (no device work queued):
  *                   M not in {8,16,32,64}, K not in {0,1,2,4,8} or not
  *                   dividing M, n >= 2^30, head >= n, null pointer,
+ *                   an unknown flag bit or PBIT_SIGNED with PBIT_FLOAT,
  *                   workspace too small (see PBIT_ENOMEM);
  *   PBIT_EMALFORMED found on the device: an index >= n, a cycle, or a list
  *                   whose length from head is not n; next[] is left as it
@@ -59,7 +65,8 @@ enum {
 enum {
     PBIT_ASCENDING = 0,
     PBIT_DESCENDING = 1, /* Sec. 6: largest key first                 */
-    PBIT_SIGNED = 2      /* Sec. 7-8: two's-complement keys           */
+    PBIT_SIGNED = 2,     /* Sec. 7-8: two's-complement keys           */
+    PBIT_FLOAT = 4       /* Sec. 14: IEEE-754 sign-magnitude keys     */
 };
 
 /*
@@ -175,6 +182,31 @@ int pbit_sort_lists_profiled(const uint32_t *d_heads, const uint64_t *d_offsets,
                              uint32_t flags, uint32_t *d_new_heads, int32_t *d_status, void *ws,
                              size_t ws_bytes, void *stream, void **events, int32_t *stage_ids,
                              int n_events, int *n_recorded);
+
+/*
+ * Doubly-linked lists (Sec. 13).  The sort relinks only next[]; this call then
+ * rebuilds the backward links: prev[next[i]] = i for every node i with a
+ * successor and prev[h] = PBIT_NIL for every head h in d_heads.  The paper
+ * walks each list from its head; since a node's backward link depends only on
+ * the forward link into it, the device does it as one scatter over all n
+ * nodes, and one call serves a single list or a whole batch.
+ *   d_heads    device uint32[num_lists] heads (PBIT_NIL entries are skipped):
+ *              the d_result word of pbit_sort_list_async (num_lists = 1) or
+ *              the d_new_heads of pbit_sort_lists, used straight after them on
+ *              the same stream;
+ *   next, prev device uint32[n], distinct arrays; every node must be on one
+ *              of the lists (prev of a node on none is not written);
+ *   d_status   optional (NULL) device int32: when non-zero on entry (a sort
+ *              that found a malformed list) nothing is written; an index >= n
+ *              in next[] or d_heads is skipped and sets PBIT_EMALFORMED.
+ *              For a single list pass d_result + 1.
+ * Asynchronous on `stream`; returns PBIT_EINVAL (n >= 2^32 - 1, null or
+ * misaligned pointer, next == prev) with nothing queued, else PBIT_OK or
+ * PBIT_EHIP.  Gather-form lists (local indices) are repaired one list at a
+ * time with that list's arrays and n = its length.
+ */
+int pbit_repair_prev_async(const uint32_t *d_heads, uint32_t num_lists, const uint32_t *next,
+                           uint32_t *prev, uint64_t n, int32_t *d_status, void *stream);
 
 /* Human-readable text for a status code. */
 const char *pbit_status_string(int code);

@@ -20,6 +20,7 @@ NIL = 0xFFFFFFFF
 FLAG_LIFO = 1
 FLAG_DESCENDING = 2
 FLAG_SIGNED = 4
+FLAG_FLOAT = 8
 
 OK, EINVAL, EMALFORMED, ENOMEM = 0, -1, -2, -3
 
@@ -62,6 +63,9 @@ def _load():
             ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, u32p]
         lib.pbit_oracle_list_order.restype = ctypes.c_int64
         lib.pbit_oracle_list_order.argtypes = [
+            ctypes.c_uint32, u32p, ctypes.c_uint64, u32p]
+        lib.pbit_oracle_repair_prev.restype = ctypes.c_int64
+        lib.pbit_oracle_repair_prev.argtypes = [
             ctypes.c_uint32, u32p, ctypes.c_uint64, u32p]
         _lib = lib
     return _lib
@@ -126,3 +130,17 @@ def list_order(head: int, next_: np.ndarray) -> np.ndarray:
     if t < 0:
         raise ValueError("malformed list (status %d)" % t)
     return out[:t]
+
+
+def repair_prev(head: int, next_: np.ndarray, prev: np.ndarray | None = None) -> np.ndarray:
+    """Backward links of the list (Sec. 13): returns a prev[] array (a copy of
+    ``prev`` or, by default, all NIL) with every node on the list pointed at
+    the node before it; raises on a malformed list."""
+    lib = _load()
+    nxt = np.ascontiguousarray(next_, dtype=np.uint32)
+    out = (np.full(nxt.shape[0], NIL, dtype=np.uint32) if prev is None
+           else np.array(prev, dtype=np.uint32, copy=True))
+    t = lib.pbit_oracle_repair_prev(int(head) & 0xFFFFFFFF, _u32p(nxt), nxt.shape[0], _u32p(out))
+    if t < 0:
+        raise ValueError("malformed list (status %d)" % t)
+    return out

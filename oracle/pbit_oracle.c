@@ -30,6 +30,15 @@
  *   - signed keys (Sec. 7-8): the list is split into negative and
  *     non-negative keys keeping list order, each part is sorted as unsigned
  *     and the parts are concatenated (negatives first when ascending).
+ *   - floating-point keys (Sec. 14): the stored M bits are an IEEE-754 style
+ *     sign-magnitude number (sign, then characteristic, then mantissa).  The
+ *     paper sorts on the mantissa first and then, stably, on the
+ *     characteristic; for non-negative numbers that is one sort on the whole
+ *     bit pattern, done here.  The paper does not treat negative numbers: they
+ *     are split off by the sign bit as in Sec. 8, and since a larger
+ *     magnitude means a smaller value, the negative part is sorted on its
+ *     pattern in the opposite direction before the parts are joined.  So -0
+ *     comes before +0, and NaNs go to the ends by their sign bit.
  *   - M is the storage width of a key in bits (8, 16, 32 or 64); K must
  *     divide M.  An empty list returns NIL and writes nothing.
  *
@@ -52,7 +61,8 @@ enum {
 enum {
     ORACLE_FLAG_LIFO = 1,       /* push-front groups, as in the printed listings */
     ORACLE_FLAG_DESCENDING = 2, /* Sec. 6: largest key first                      */
-    ORACLE_FLAG_SIGNED = 4      /* Sec. 7-8: two's-complement keys               */
+    ORACLE_FLAG_SIGNED = 4,     /* Sec. 7-8: two's-complement keys               */
+    ORACLE_FLAG_FLOAT = 8       /* Sec. 14: sign-magnitude floating-point keys   */
 };
 
 typedef struct {
@@ -212,7 +222,11 @@ int64_t pbit_oracle_sort(uint32_t head, uint32_t *next, const void *keys, uint64
         return ORACLE_ENOMEM;
 
     uint32_t P;
-    if (flags & ORACLE_FLAG_SIGNED) {
+    if ((flags & ORACLE_FLAG_SIGNED) && (flags & ORACLE_FLAG_FLOAT)) {
+        free(c.roots);
+        return ORACLE_EINVAL;
+    }
+    if (flags & (ORACLE_FLAG_SIGNED | ORACLE_FLAG_FLOAT)) {
         /* Sec. 8: split by sign (list order kept), sort each part unsigned,
          * then join: negatives before non-negatives when ascending. */
         uint32_t nh = ORACLE_NIL, nt = ORACLE_NIL, ph = ORACLE_NIL, pt = ORACLE_NIL;
@@ -230,10 +244,21 @@ int64_t pbit_oracle_sort(uint32_t head, uint32_t *next, const void *keys, uint64
             }
             i = following;
         }
-        if (c.descending)
-            P = oracle_pbit(&c, ph, M, oracle_pbit(&c, nh, M, ORACLE_NIL));
-        else
-            P = oracle_pbit(&c, nh, M, oracle_pbit(&c, ph, M, ORACLE_NIL));
+        /* A negative float's pattern grows with its magnitude, so its part
+         * runs in the direction opposite to the requested one. */
+        int flip = (flags & ORACLE_FLAG_FLOAT) != 0;
+        int desc = c.descending;
+        if (!desc) {
+            c.descending = 0;
+            P = oracle_pbit(&c, ph, M, ORACLE_NIL);
+            c.descending = flip;
+            P = oracle_pbit(&c, nh, M, P);
+        } else {
+            c.descending = !flip;
+            P = oracle_pbit(&c, nh, M, ORACLE_NIL);
+            c.descending = 1;
+            P = oracle_pbit(&c, ph, M, P);
+        }
     } else {
         P = oracle_pbit(&c, head, M, ORACLE_NIL);
     }
@@ -312,4 +337,28 @@ int64_t pbit_oracle_list_order(uint32_t head, const uint32_t *next, uint64_t n, 
     for (uint32_t i = head; i != ORACLE_NIL; i = next[i])
         order[t++] = i;
     return (int64_t)t;
+}
+
+/* Sec. 13, doubly-linked lists: the sort relinks only next[]; afterwards a
+ * repair walks the list from its head and points each node's backward link at
+ * the node met just before it (NIL for the head).  prev[] entries of nodes not
+ * on the list are left alone.  Returns the number of nodes walked or a
+ * negative status (nothing is written then). */
+int64_t pbit_oracle_repair_prev(uint32_t head, const uint32_t *next, uint64_t n, uint32_t *prev)
+{
+    if (head == ORACLE_NIL)
+        return 0;
+    if (n == 0 || head >= n)
+        return ORACLE_EINVAL;
+    uint64_t steps = 0;
+    for (uint32_t i = head; i != ORACLE_NIL; i = next[i]) {
+        if (i >= n || ++steps > n)
+            return ORACLE_EMALFORMED;
+    }
+    uint32_t behind = ORACLE_NIL;
+    for (uint32_t i = head; i != ORACLE_NIL; i = next[i]) {
+        prev[i] = behind;
+        behind = i;
+    }
+    return (int64_t)steps;
 }

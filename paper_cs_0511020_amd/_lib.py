@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libpbit.so")
 NIL = 0xFFFFFFFF
 MAX_NODES = (1 << 30) - 1
 OK, EINVAL, EMALFORMED, ENOMEM, EHIP = 0, -1, -2, -3, -4
-ASCENDING, DESCENDING, SIGNED = 0, 1, 2
+ASCENDING, DESCENDING, SIGNED, FLOAT = 0, 1, 2, 4
 
 # name -> (restype, argtypes)
 _SIGNATURES = {
@@ -48,6 +48,9 @@ _SIGNATURES = {
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    "pbit_repair_prev_async": (ctypes.c_int, [
+        ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+        ctypes.c_void_p, ctypes.c_void_p]),
     "pbit_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "pbit_version": (ctypes.c_char_p, []),
 }
@@ -123,3 +126,13 @@ def sort_list(head: int, next_, keys, M: int, K: int = 0) -> int:
     n = int(next_.numel())
     return int(load().pbit_sort_list(int(head) & 0xFFFFFFFF, _ptr(next_), _ptr(keys), n,
                                       int(M), int(K)))
+
+
+def repair_prev(heads, num_lists: int, next_, prev, n: int, status=None, status_offset: int = 0,
+                stream=None) -> int:
+    """Raw C-ABI call of the backward-link repair (``status_offset`` bytes into
+    ``status``: 4 selects the status word of a single-list result)."""
+    st_ptr = _ptr(status) + status_offset if status is not None else 0
+    return int(load().pbit_repair_prev_async(
+        _ptr(heads), int(num_lists), _ptr(next_), _ptr(prev), int(n), st_ptr,
+        _stream_handle(stream)))

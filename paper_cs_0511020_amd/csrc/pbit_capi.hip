@@ -19,6 +19,8 @@ hipError_t enqueue_sort_lists(const Plan& P, const uint32_t* heads, const uint64
                               const uint64_t* next_in_ptrs, const uint64_t* next_out_ptrs,
                               const uint64_t* key_ptrs, uint32_t* new_heads, int32_t* d_status,
                               char* ws, hipStream_t s, Prof* prof);
+hipError_t enqueue_repair_prev(const uint32_t* heads, uint32_t num_lists, const uint32_t* next,
+                               uint32_t* prev, uint32_t n, int32_t* status, hipStream_t s);
 uint32_t pass_tile(uint32_t key_bytes);
 
 static size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
@@ -48,7 +50,8 @@ static bool valid_shape(uint32_t M, uint32_t K)
 static bool plan_common(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, uint32_t lid_passes,
                         size_t lw_bytes, uint64_t level0_chains, uint32_t cap, Plan* P, size_t& off)
 {
-    if (!valid_shape(M, K) || (flags & ~(uint32_t)(PBIT_DESCENDING | PBIT_SIGNED)) != 0)
+    if (!valid_shape(M, K) || (flags & ~(uint32_t)(PBIT_DESCENDING | PBIT_SIGNED | PBIT_FLOAT)) != 0 ||
+        ((flags & PBIT_SIGNED) && (flags & PBIT_FLOAT)))
         return false;
     P->n = n;
     P->M = M;
@@ -270,6 +273,28 @@ extern "C" int pbit_sort_list_profiled(uint32_t head, const uint32_t* next_in,
                                   ws_bytes, stream, &prof);
     *n_recorded = prof.count;
     return st;
+}
+
+extern "C" int pbit_repair_prev_async(const uint32_t* d_heads, uint32_t num_lists,
+                                      const uint32_t* next, uint32_t* prev, uint64_t n,
+                                      int32_t* d_status, void* stream)
+{
+    if (n >= (uint64_t)PBIT_NIL)
+        return PBIT_EINVAL;
+    if (n == 0 && num_lists == 0)
+        return PBIT_OK;
+    if (num_lists && !d_heads)
+        return PBIT_EINVAL;
+    if (n && (!next || !prev))
+        return PBIT_EINVAL;
+    if (next && prev && (const void*)next == (const void*)prev)
+        return PBIT_EINVAL;
+    if (((uintptr_t)d_heads & 3u) || ((uintptr_t)next & 3u) || ((uintptr_t)prev & 3u) ||
+        ((uintptr_t)d_status & 3u))
+        return PBIT_EINVAL;
+    hipError_t e = enqueue_repair_prev(d_heads, num_lists, next, prev, (uint32_t)n, d_status,
+                                       (hipStream_t)stream);
+    return e == hipSuccess ? PBIT_OK : PBIT_EHIP;
 }
 
 extern "C" const char* pbit_stage_name(int stage)

@@ -136,7 +136,8 @@ template <typename KeyT> struct GatherSrc {
 // Node records, the count of every pattern value of every key pass, the NIL
 // count and the hash sums sum h(next) - sum h(i).
 template <typename KeyT, int RB, class Src>
-__global__ __launch_bounds__(256) void k_pack(Src src, uint32_t n, KeyT xor_mask, uint32_t passes,
+__global__ __launch_bounds__(256) void k_pack(Src src, uint32_t n, KeyT float_sel, KeyT xor_mask,
+                                              uint32_t passes,
                                               NodeRec<KeyT>* __restrict__ nodes,
                                               uint32_t* __restrict__ hist, Header* hdr)
 {
@@ -154,6 +155,14 @@ __global__ __launch_bounds__(256) void k_pack(Src src, uint32_t n, KeyT xor_mask
         uint32_t nx;
         KeyT k;
         src.load(i, n, nx, k, bad);
+        // Floating-point keys (sign-magnitude): a negative pattern is inverted
+        // whole, a non-negative one gets its sign bit set, so unsigned order of
+        // the result is the numeric order.  float_sel is all ones or zero.
+        {
+            constexpr uint32_t W = sizeof(KeyT) * 8;
+            const KeyT neg = (KeyT)((KeyT)0 - (KeyT)(k >> (W - 1)));
+            k ^= (KeyT)((KeyT)(neg | (KeyT)((KeyT)1 << (W - 1))) & float_sel);
+        }
         k ^= xor_mask;
         if (nx == kNil) {
             nils++;

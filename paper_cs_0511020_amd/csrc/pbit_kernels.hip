@@ -439,4 +439,54 @@ hipError_t enqueue_empty(uint32_t* d_result, hipStream_t s)
     return hipGetLastError();
 }
 
+// Backward links of doubly-linked lists (Sec. 13).  Each node's backward link
+// is fixed by its own forward link alone, so the walk from the head becomes one
+// scatter: prev[next[i]] = i over every node, and NIL for every head.  next[]
+// is read in index order (coalesced); the prev[] writes land in random lines.
+// A non-zero status on entry (a sort that found a malformed list) leaves prev[]
+// untouched; an index >= n is skipped and reported.
+__global__ __launch_bounds__(256) void k_repair_prev(const uint32_t* __restrict__ heads,
+                                                     uint32_t num_lists,
+                                                     const uint32_t* __restrict__ next,
+                                                     uint32_t* __restrict__ prev, uint32_t n,
+                                                     int32_t* status)
+{
+    if (status && ld_agent(status) != 0)
+        return;
+    bool bad = false;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint32_t i = tid; i < n; i += stride) {
+        const uint32_t nx = next[i];
+        if (nx == kNil)
+            continue;
+        if (nx < n)
+            prev[nx] = i;
+        else
+            bad = true;
+    }
+    for (uint32_t l = tid; l < num_lists; l += stride) {
+        const uint32_t h = heads[l];
+        if (h == kNil)
+            continue;
+        if (h < n)
+            prev[h] = kNil;
+        else
+            bad = true;
+    }
+    if (bad && status)
+        set_error(status, PBIT_EMALFORMED);
+}
+
+hipError_t enqueue_repair_prev(const uint32_t* heads, uint32_t num_lists, const uint32_t* next,
+                               uint32_t* prev, uint32_t n, int32_t* status, hipStream_t s)
+{
+    const uint64_t work = (uint64_t)(n > num_lists ? n : num_lists);
+    const uint64_t want = (work + 255) / 256;
+    const uint32_t blocks = (uint32_t)(want < 8192 ? (want ? want : 1) : 8192);
+    hipLaunchKernelGGL(k_repair_prev, dim3(blocks), dim3(256), 0, s, heads, num_lists, next, prev,
+                       n, status);
+    return hipGetLastError();
+}
+
 }  // namespace pbit

@@ -29,6 +29,7 @@ template <typename KeyT, int RB, class Src>
 static hipError_t launch_pack_rb(const Plan& P, const Src& src, char* ws, hipStream_t s)
 {
     KeyT mask = 0;
+    const KeyT float_sel = (P.flags & PBIT_FLOAT) ? (KeyT)~(KeyT)0 : (KeyT)0;
     if (P.flags & PBIT_SIGNED)
         mask ^= (KeyT)((KeyT)1 << (sizeof(KeyT) * 8 - 1));
     if (P.flags & PBIT_DESCENDING)
@@ -37,7 +38,7 @@ static hipError_t launch_pack_rb(const Plan& P, const Src& src, char* ws, hipStr
     const uint32_t blocks = (uint32_t)(want < 1024 ? want : 1024);
     const size_t shm = (size_t)P.key_passes * P.radix * sizeof(uint32_t);
     hipLaunchKernelGGL((k_pack<KeyT, RB, Src>), dim3(blocks), dim3(256), shm, s, src,
-                       (uint32_t)P.n, mask, P.key_passes, (NodeRec<KeyT>*)(ws + P.o_nodes),
+                       (uint32_t)P.n, float_sel, mask, P.key_passes, (NodeRec<KeyT>*)(ws + P.o_nodes),
                        (uint32_t*)(ws + P.o_hist), (Header*)(ws + P.o_header));
     return hipGetLastError();
 }

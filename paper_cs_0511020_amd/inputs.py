@@ -84,6 +84,45 @@ def few_distinct_keys(n: int, rng: np.random.Generator, count: int = 8,
     return values[rng.integers(0, count, size=n)]
 
 
+FLOAT_DTYPES = {16: np.float16, 32: np.float32, 64: np.float64}
+
+
+def float_keys(n: int, M: int, rng: np.random.Generator, specials: bool = True) -> np.ndarray:
+    """IEEE-754 keys of width M (binary16/32/64), returned as their bit
+    patterns in the unsigned M-bit dtype.  Values of both signs spread over the
+    whole exponent range (log-uniform magnitudes), a pool of repeated values,
+    and, with ``specials``, a sprinkling of +-0, subnormals, +-inf and NaNs of
+    both signs."""
+    ft = FLOAT_DTYPES[M]
+    fi = np.finfo(ft)
+    lo, hi = np.log2(float(fi.tiny)), np.log2(float(fi.max)) - 1.0
+    mag = np.exp2(rng.uniform(lo, hi, size=n))
+    sign = np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    vals = (sign * mag).astype(ft)
+    pool = vals[rng.integers(0, max(1, n), size=max(1, n // 16))] if n else vals
+    rep = rng.random(n) < 0.25
+    if n:
+        vals[rep] = pool[rng.integers(0, pool.shape[0], size=int(rep.sum()))]
+    bits = vals.view(KEY_DTYPES[M]).copy()
+    if specials and n:
+        one = KEY_DTYPES[M](1)
+        top = KEY_DTYPES[M](one << KEY_DTYPES[M](M - 1))
+        nm = fi.nmant
+        exp_all = KEY_DTYPES[M](((1 << (M - 1 - nm)) - 1) << nm)
+        choices = [
+            KEY_DTYPES[M](0), top,                          # +0, -0
+            one, top | one,                                 # smallest subnormals
+            exp_all, top | exp_all,                         # +inf, -inf
+            exp_all | one, top | exp_all | one,             # NaNs of both signs
+            exp_all | KEY_DTYPES[M](1 << (nm - 1)),         # quiet NaN
+            top | exp_all | KEY_DTYPES[M]((1 << nm) - 1),   # NaN, all mantissa bits
+        ]
+        sp = rng.random(n) < 0.02
+        bits[sp] = np.asarray(choices, dtype=KEY_DTYPES[M])[rng.integers(0, len(choices),
+                                                                          size=int(sp.sum()))]
+    return bits
+
+
 def c2_keys(dist: str, n: int, rng: np.random.Generator) -> np.ndarray:
     if dist == "uniform":
         return uniform_keys(n, 32, rng)

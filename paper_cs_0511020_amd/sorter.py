@@ -12,7 +12,8 @@ import torch
 from . import _lib
 
 _KEY_BITS = {torch.uint8: 8, torch.int8: 8, torch.int16: 16, torch.uint16: 16,
-             torch.int32: 32, torch.uint32: 32, torch.int64: 64, torch.uint64: 64}
+             torch.int32: 32, torch.uint32: 32, torch.int64: 64, torch.uint64: 64,
+             torch.float16: 16, torch.bfloat16: 16, torch.float32: 32, torch.float64: 64}
 
 
 def key_bits(keys: torch.Tensor) -> int:
@@ -20,6 +21,18 @@ def key_bits(keys: torch.Tensor) -> int:
         return _KEY_BITS[keys.dtype]
     except KeyError:
         raise TypeError("unsupported key dtype %s" % keys.dtype) from None
+
+
+def key_flags(keys: torch.Tensor, descending: bool, signed: bool) -> int:
+    """Flag word for a key tensor: floating-point dtypes sort by value."""
+    flags = _lib.DESCENDING if descending else 0
+    if keys.is_floating_point():
+        if signed:
+            raise ValueError("signed applies to integer keys only")
+        flags |= _lib.FLOAT
+    elif signed:
+        flags |= _lib.SIGNED
+    return flags
 
 
 class PbitError(RuntimeError):
@@ -32,7 +45,8 @@ class ListSorter:
     """Sort singly-linked lists stored as device arrays.
 
     next: int32/uint32 tensor of n node indices (0xFFFFFFFF ends the list).
-    keys: n unsigned (or, with ``signed=True``, two's-complement) integers.
+    keys: n unsigned (or, with ``signed=True``, two's-complement) integers, or
+    floating-point values (float16/bfloat16/float32/float64), sorted by value.
     """
 
     def __init__(self, device="cuda"):
@@ -54,8 +68,12 @@ class ListSorter:
     def sort_async(self, head: int, next_in: torch.Tensor, keys: torch.Tensor, K: int = 0,
                    descending: bool = False, signed: bool = False,
                    next_out: torch.Tensor | None = None, result: torch.Tensor | None = None,
-                   stream=None) -> torch.Tensor:
-        """Queue the sort; returns the 2-word device result {head, status}."""
+                   stream=None, prev_out: torch.Tensor | None = None) -> torch.Tensor:
+        """Queue the sort; returns the 2-word device result {head, status}.
+
+        With ``prev_out`` (n uint32 entries, not the next array) the list is
+        treated as doubly linked and its backward links are rebuilt after the
+        relink."""
         n = int(next_in.numel())
         M = key_bits(keys)
         if int(keys.numel()) != n:
@@ -65,18 +83,22 @@ class ListSorter:
         if result is None:
             result = self.result
         ws = self.workspace(n, M, K)
-        flags = (_lib.DESCENDING if descending else 0) | (_lib.SIGNED if signed else 0)
+        flags = key_flags(keys, descending, signed)
         st = _lib.sort_list_async(head, next_in, next_out, keys, n, M, K, flags, result, ws,
                                   self._ws_bytes, stream)
+        if st == _lib.OK and prev_out is not None:
+            st = _lib.repair_prev(result, 1, next_out, prev_out, n, result, 4, stream)
         if st != _lib.OK:
             raise PbitError(st)
         return result
 
     def sort(self, head: int, next_in: torch.Tensor, keys: torch.Tensor, K: int = 0,
              descending: bool = False, signed: bool = False,
-             next_out: torch.Tensor | None = None) -> int:
+             next_out: torch.Tensor | None = None,
+             prev_out: torch.Tensor | None = None) -> int:
         """Sort and wait; returns the new head (0xFFFFFFFF if empty)."""
-        res = self.sort_async(head, next_in, keys, K, descending, signed, next_out)
+        res = self.sort_async(head, next_in, keys, K, descending, signed, next_out,
+                              prev_out=prev_out)
         h, st = (int(x) for x in res.cpu().tolist())
         if st != 0:
             raise PbitError(st)
@@ -108,7 +130,7 @@ class ListsSorter:
 
     def sort_async(self, heads, offsets, next_in, keys, K: int = 0, descending: bool = False,
                    signed: bool = False, next_out=None, new_heads=None, status=None,
-                   stream=None):
+                   stream=None, prev_out=None):
         L = int(heads.numel())
         total = int(next_in.numel())
         M = key_bits(keys)
@@ -119,17 +141,19 @@ class ListsSorter:
         if status is None:
             status = self.status
         ws = self.workspace(total, L, M, K)
-        flags = (_lib.DESCENDING if descending else 0) | (_lib.SIGNED if signed else 0)
+        flags = key_flags(keys, descending, signed)
         st = _lib.sort_lists(heads, offsets, L, total, next_in, next_out, keys, M, K, flags,
                              new_heads, status, ws, self._ws_bytes, stream)
+        if st == _lib.OK and prev_out is not None:
+            st = _lib.repair_prev(new_heads, L, next_out, prev_out, total, status, 0, stream)
         if st != _lib.OK:
             raise PbitError(st)
         return new_heads, status
 
     def sort(self, heads, offsets, next_in, keys, K: int = 0, descending: bool = False,
-             signed: bool = False, next_out=None):
+             signed: bool = False, next_out=None, prev_out=None):
         new_heads, status = self.sort_async(heads, offsets, next_in, keys, K, descending, signed,
-                                            next_out)
+                                            next_out, prev_out=prev_out)
         st = int(status.item())
         if st != 0:
             raise PbitError(st)

@@ -19,12 +19,26 @@ def from_dev(t, dtype=np.uint32):
     return t.cpu().numpy().view(dtype)
 
 
+FLOAT_VIEW = {np.dtype(np.uint16): np.float16, np.dtype(np.uint32): np.float32,
+              np.dtype(np.uint64): np.float64}
+
+
+def keys_to_dev(keys, flags, torch):
+    """Device keys; with the floating-point flag (4) the bit patterns are
+    handed over as the float dtype of the same width, which is what selects
+    floating-point order in the binding."""
+    keys = np.ascontiguousarray(keys)
+    if flags & 4:
+        return torch.from_numpy(keys.view(FLOAT_VIEW[keys.dtype])).to("cuda")
+    return to_dev(keys, torch)
+
+
 def gpu_sort(head, nxt, keys, K, flags=0, inplace=True, sorter=None):
     import torch
     from paper_cs_0511020_amd.sorter import ListSorter
     sorter = sorter or ListSorter()
     nt = to_dev(nxt.astype(np.uint32), torch)
-    kt = to_dev(keys, torch)
+    kt = keys_to_dev(keys, flags, torch)
     out = None if inplace else torch.full_like(nt, -1)
     res = sorter.sort_async(head, nt, kt, K, descending=bool(flags & 1),
                             signed=bool(flags & 2), next_out=out)
@@ -41,6 +55,8 @@ def oracle_flags(flags, oracle):
         f |= oracle.FLAG_DESCENDING
     if flags & 2:
         f |= oracle.FLAG_SIGNED
+    if flags & 4:
+        f |= oracle.FLAG_FLOAT
     return f
 
 

@@ -72,6 +72,7 @@ def test_host_argument_checks(lib):
     assert _call(lib, K=3) == E
     assert _call(lib, M=8, K=16) == E
     assert _call(lib, flags=8) == E
+    assert _call(lib, flags=_lib.SIGNED | _lib.FLOAT) == E
     assert _call(lib, res=0) == E
     assert _call(lib, res=0x2002) == E            # misaligned result
     assert _call(lib, head=8, n=8) == E           # head out of range
@@ -88,6 +89,18 @@ def test_host_argument_checks(lib):
     assert lib.pbit_sort_list(9, 0x1000, 0x1000, 8, 32, 4) == E
     assert lib.pbit_sort_list(0, 0, 0x1000, 8, 32, 4) == E
     assert lib.pbit_sort_list(_lib.NIL, 0, 0, 0, 32, 4) == _lib.NIL
+
+
+def test_repair_prev_host_checks(lib):
+    E = _lib.EINVAL
+    f = lib.pbit_repair_prev_async
+    assert f(0x1000, 1, 0x2000, 0x3000, 1 << 32, 0, None) == E      # n too large
+    assert f(0, 1, 0x2000, 0x3000, 8, 0, None) == E                 # heads missing
+    assert f(0x1000, 1, 0, 0x3000, 8, 0, None) == E                 # next missing
+    assert f(0x1000, 1, 0x2000, 0x2000, 8, 0, None) == E            # prev aliases next
+    assert f(0x1000, 1, 0x2002, 0x3000, 8, 0, None) == E            # misaligned next
+    assert f(0x1000, 1, 0x2000, 0x3000, 8, 0x4001, None) == E       # misaligned status
+    assert f(0, 0, 0, 0, 0, 0, None) == _lib.OK                     # nothing to do
 
 
 def test_lists_host_checks(lib):
@@ -107,5 +120,6 @@ def test_lists_host_checks(lib):
     assert call(offs=0x2004) == E      # offsets must be 8-byte aligned
     assert call(st=0) == E
     assert call(nin=0) == E
-    assert call(flags=4) == E
+    assert call(flags=8) == E
+    assert call(flags=_lib.SIGNED | _lib.FLOAT) == E
     assert call(wsb=100) == _lib.ENOMEM

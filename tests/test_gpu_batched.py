@@ -6,7 +6,7 @@ import pytest
 
 from paper_cs_0511020_amd import inputs
 
-from .gpu_util import NIL, to_dev
+from .gpu_util import NIL, keys_to_dev, oracle_flags, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -31,7 +31,7 @@ def gpu_sort_lists(heads, offsets, nxt, keys, K, flags=0, inplace=False):
     ht = to_dev(heads.astype(np.uint32), torch)
     ot = torch.from_numpy(np.asarray(offsets, dtype=np.int64)).to("cuda")
     nt = to_dev(nxt.astype(np.uint32), torch)
-    kt = to_dev(keys, torch)
+    kt = keys_to_dev(keys, flags, torch)
     out = None if inplace else torch.full_like(nt, -1)
     new_heads, status = s.sort_async(ht, ot, nt, kt, K, descending=bool(flags & 1),
                                      signed=bool(flags & 2), next_out=out)
@@ -43,7 +43,7 @@ def gpu_sort_lists(heads, offsets, nxt, keys, K, flags=0, inplace=False):
 
 def oracle_lists(oracle_mod, heads, offsets, nxt, keys, K, flags=0):
     M = keys.dtype.itemsize * 8
-    f = (oracle_mod.FLAG_DESCENDING if flags & 1 else 0) | (oracle_mod.FLAG_SIGNED if flags & 2 else 0)
+    f = oracle_flags(flags, oracle_mod)
     st, out, nh = oracle_mod.sort_lists(heads, offsets, nxt, keys, M, K, flags=f)
     assert st == 0
     return nh, out
@@ -96,6 +96,10 @@ def test_key_widths(oracle_mod, M, K):
     check(oracle_mod, heads, offs, nxt, keys, K)
     if M == 32:
         check(oracle_mod, heads, offs, nxt, keys, K, flags=3)
+    if M >= 16:
+        fkeys = inputs.float_keys(nxt.shape[0], M, rng)
+        check(oracle_mod, heads, offs, nxt, fkeys, K, flags=4)
+        check(oracle_mod, heads, offs, nxt, fkeys, K, flags=5)
 
 
 def test_many_lists_three_id_passes(oracle_mod):

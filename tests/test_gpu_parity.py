@@ -108,6 +108,19 @@ def test_descending_signed(oracle_mod, flags):
         run_parity(oracle_mod, head, nxt, keys, 4, flags=flags)
 
 
+@pytest.mark.parametrize("M", [16, 32, 64])
+def test_float_keys(oracle_mod, M):
+    """IEEE keys with +-0, subnormals, infinities, NaNs of both signs and repeats."""
+    rng = inputs.rng_for(80 + M)
+    for n in (1, 777, 20011):
+        nxt, head, _ = inputs.random_list(n, rng)
+        keys = inputs.float_keys(n, M, rng)
+        for K in (4, 8):
+            for flags in (4, 5):
+                say("float M=%d n=%d K=%d flags=%d" % (M, n, K, flags))
+                run_parity(oracle_mod, head, nxt, keys, K, flags=flags)
+
+
 def test_special_layouts(oracle_mod):
     rng = inputs.rng_for(61)
     n = 50000

@@ -276,3 +276,132 @@ def test_list_order(oracle_mod):
     rng = inputs.rng_for(41)
     nxt, head, order = inputs.random_list(999, rng)
     assert np.array_equal(oracle_mod.list_order(head, nxt), order)
+
+
+def float_value_key(b, M):
+    """The order the floating-point reading defines, computed from the values:
+    numeric order, -0 before +0, NaNs outside the infinities on the side of
+    their sign bit (a larger payload further out)."""
+    import math
+    ft = inputs.FLOAT_DTYPES[M]
+    b = int(b)
+    v = float(np.array([b], dtype=inputs.KEY_DTYPES[M]).view(ft)[0])
+    neg = (b >> (M - 1)) & 1
+    if math.isnan(v):
+        payload = b & ((1 << (M - 1)) - 1)
+        return (0, -payload, 0) if neg else (2, payload, 0)
+    return (1, v, 0 if neg else 1)
+
+
+@pytest.mark.parametrize("M", [16, 32, 64])
+def test_float_keys_against_value_order(oracle_mod, M):
+    rng = inputs.rng_for(700 + M)
+    n = 3000
+    nxt, head, order = inputs.random_list(n, rng)
+    keys = inputs.float_keys(n, M, rng)
+    vk = [float_value_key(k, M) for k in keys]
+    for K in (4, 8):
+        for flags, desc in [(oracle_mod.FLAG_FLOAT, False),
+                            (oracle_mod.FLAG_FLOAT | oracle_mod.FLAG_DESCENDING, True)]:
+            h, out = oracle_mod.sort_list(head, nxt, keys, M, K, flags=flags)
+            exp = sorted(order.tolist(), key=lambda i: vk[i], reverse=desc)
+            assert walk(h, out) == exp, (M, K, desc)
+
+
+def test_float_finite_against_numpy(oracle_mod):
+    """Finite non-zero values: numpy's stable argsort of the values themselves."""
+    rng = inputs.rng_for(711)
+    for M in (16, 32, 64):
+        n = 2000
+        nxt, head, order = inputs.random_list(n, rng)
+        keys = inputs.float_keys(n, M, rng, specials=False)
+        vals = keys.view(inputs.FLOAT_DTYPES[M])[order]
+        assert np.all(np.isfinite(vals)) and np.all(vals != 0)
+        h, out = oracle_mod.sort_list(head, nxt, keys, M, 8, flags=oracle_mod.FLAG_FLOAT)
+        assert walk(h, out) == order[np.argsort(vals, kind="stable")].tolist()
+        h, out = oracle_mod.sort_list(head, nxt, keys, M, 8,
+                                      flags=oracle_mod.FLAG_FLOAT | oracle_mod.FLAG_DESCENDING)
+        assert walk(h, out) == order[np.argsort(-vals, kind="stable")].tolist()
+
+
+def test_float_hand_order(oracle_mod):
+    """binary32 specials in a fixed scrambled list; the expected order is written out."""
+    pats = {
+        "-nan": 0xFFC00000, "-inf": 0xFF800000, "-3.5": 0xC0600000, "-den": 0x80000001,
+        "-0": 0x80000000, "+0": 0x00000000, "+den": 0x00000001, "2": 0x40000000,
+        "+inf": 0x7F800000, "+nan": 0x7FC00000,
+    }
+    names = ["2", "-0", "+nan", "-3.5", "+den", "-inf", "+0", "-nan", "+inf", "-den"]
+    keys = np.array([pats[x] for x in names], dtype=np.uint32)
+    nxt, head, _ = inputs.identity_list(len(names))
+    h, out = oracle_mod.sort_list(head, nxt, keys, 32, 8, flags=oracle_mod.FLAG_FLOAT)
+    assert [names[i] for i in walk(h, out)] == [
+        "-nan", "-inf", "-3.5", "-den", "-0", "+0", "+den", "2", "+inf", "+nan"]
+    h, out = oracle_mod.sort_list(head, nxt, keys, 32, 4,
+                                  flags=oracle_mod.FLAG_FLOAT | oracle_mod.FLAG_DESCENDING)
+    assert [names[i] for i in walk(h, out)] == [
+        "+nan", "+inf", "2", "+den", "+0", "-0", "-den", "-3.5", "-inf", "-nan"]
+
+
+@pytest.mark.parametrize("M", [16, 32, 64])
+def test_float_two_pass_reading(oracle_mod, M):
+    """Sec. 14 sorts non-negative floats on the mantissa, then stably on the
+    characteristic; two unsigned sorts on those fields give the same list as
+    one floating-point sort."""
+    rng = inputs.rng_for(720 + M)
+    n = 2500
+    nxt, head, order = inputs.random_list(n, rng)
+    keys = inputs.float_keys(n, M, rng)
+    top = inputs.KEY_DTYPES[M](1) << inputs.KEY_DTYPES[M](M - 1)
+    keys = keys & ~top  # non-negative: clear the sign bit
+    nm = np.finfo(inputs.FLOAT_DTYPES[M]).nmant
+    mant = keys & inputs.KEY_DTYPES[M]((1 << nm) - 1)
+    char_w = {16: 8, 32: 8, 64: 16}[M]
+    char = (keys >> inputs.KEY_DTYPES[M](nm)).astype(inputs.KEY_DTYPES[char_w])
+    h1, o1 = oracle_mod.sort_list(head, nxt, mant, M, 8)
+    h2, o2 = oracle_mod.sort_list(h1, o1, char, char_w, 8)
+    hf, of = oracle_mod.sort_list(head, nxt, keys, M, 8, flags=oracle_mod.FLAG_FLOAT)
+    assert h2 == hf and np.array_equal(o2, of)
+    assert walk(hf, of) == sorted(order.tolist(), key=lambda i: float_value_key(keys[i], M))
+
+
+def test_float_and_signed_rejected(oracle_mod):
+    nxt, head, _ = inputs.identity_list(4)
+    keys = np.arange(4, dtype=np.uint32)
+    h, _ = oracle_mod.sort_list(head, nxt, keys, 32, 8,
+                                flags=oracle_mod.FLAG_FLOAT | oracle_mod.FLAG_SIGNED)
+    assert h == oracle_mod.EINVAL
+
+
+def test_repair_prev_reverses_the_walk(oracle_mod):
+    """Sec. 13: after the repair, walking backward from the tail meets the
+    nodes of the forward walk in reverse, and the head's backward link is NIL."""
+    rng = inputs.rng_for(730)
+    for n in (1, 2, 3, 50, 4097):
+        nxt, head, order = inputs.random_list(n, rng)
+        keys = inputs.uniform_keys(n, 16, rng)
+        h, out = oracle_mod.sort_list(head, nxt, keys, 16, 4)
+        prev = oracle_mod.repair_prev(h, out)
+        fwd = walk(h, out)
+        back, i = [], fwd[-1]
+        while i != NIL:
+            back.append(i)
+            i = int(prev[i])
+            assert len(back) <= n
+        assert back == fwd[::-1]
+        assert prev[h] == NIL
+        # brute force: the predecessor of j is the one node whose next is j
+        for j in fwd[1:]:
+            assert np.nonzero(out == j)[0].tolist() == [int(prev[j])]
+
+
+def test_repair_prev_hand_case_and_errors(oracle_mod):
+    # list 2 -> 0 -> 3 -> 1; node 4 is not on it and keeps its value
+    nxt = np.array([3, NIL, 0, 1, NIL], dtype=np.uint32)
+    prev = oracle_mod.repair_prev(2, nxt, prev=np.full(5, 77, dtype=np.uint32))
+    assert prev.tolist() == [2, 3, NIL, 0, 77]
+    with pytest.raises(ValueError):
+        oracle_mod.repair_prev(0, np.array([1, 0], dtype=np.uint32))   # cycle
+    with pytest.raises(ValueError):
+        oracle_mod.repair_prev(0, np.array([5, NIL], dtype=np.uint32))  # index out of range
+    assert oracle_mod.repair_prev(NIL, np.zeros(0, dtype=np.uint32)).shape == (0,)
