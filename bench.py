@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--served", default="small", choices=["none", "small", "full"],
                     help="served section: 300 requests up to 2^20 nodes (small) or 2000 up "
                          "to 2^24 (full)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the float-key sort and the backward-link repair timings")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -189,6 +191,73 @@ def run_plain(args, lib, torch, np, inputs, bytemodel, EventPool):
         "value": n / (wall_ms * 1e-3) / 1e6, "wall_ms": wall_ms, "p50": p50, "p99": p99,
         "roofline": roofline, "stage_ms": stage_ms, "launches": launches, "correct": ok,
         "path_bpn": path_bpn, "path_frac": path_frac, "Keff": Keff, "src_hash": src_hash,
+    }
+
+
+def run_extras(args, lib, torch, np, inputs, bytemodel):
+    """Floating-point keys (binary32, both signs, repeats) through the whole
+    path, and the backward-link repair kernel of doubly-linked lists on the
+    sorted result; each timed with events on the stream it runs on."""
+    from paper_cs_0511020_amd import _lib
+    dev = torch.device("cuda:0")
+    n, K = args.n, args.K
+    rng = inputs.rng_for(2301)
+    nxt, head, order = inputs.random_list(n, rng)
+    keys = inputs.float_keys(n, 32, rng, specials=False)
+    next_in = torch.from_numpy(nxt.view(np.int32)).to(dev)
+    next_out = torch.empty_like(next_in)
+    prev = torch.empty_like(next_in)
+    keys_d = torch.from_numpy(keys.view(np.float32)).to(dev)
+    ws_bytes = _lib.workspace_bytes(n, 32, K)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    result = torch.zeros(2, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    steps = max(3, args.steps // 3)
+
+    def sort():
+        st = _lib.sort_list_async(head, next_in, next_out, keys_d, n, 32, K, _lib.FLOAT, result,
+                                  ws, ws_bytes, stream)
+        if st != 0:
+            raise RuntimeError("float sort failed: " + _lib.status_string(st))
+
+    def repair():
+        st = _lib.repair_prev(result, 1, next_out, prev, n, result, 4, stream)
+        if st != 0:
+            raise RuntimeError("repair failed: " + _lib.status_string(st))
+
+    def timed(fn):
+        for _ in range(2):
+            fn()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
+        for k in range(steps):
+            ev[2 * k].record(stream)
+            fn()
+            ev[2 * k + 1].record(stream)
+        torch.cuda.synchronize()
+        return statistics.median(ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(steps))
+
+    sort_ms = timed(sort)
+    rep_ms = timed(repair)
+    h = int(result[0].item()) & 0xFFFFFFFF
+    got = next_out.cpu().numpy().view(np.uint32)
+    vals = keys.view(np.float32)
+    exp = order[np.argsort(vals[order], kind="stable")]
+    ok_sort = h == int(exp[0]) and bool(np.array_equal(got[exp[:-1]], exp[1:]))
+    pv = prev.cpu().numpy().view(np.uint32)
+    ok_prev = bool(np.array_equal(pv[exp[1:]], exp[:-1])) and int(pv[exp[0]]) == 0xFFFFFFFF
+    rep_bytes = 8 * n + 4
+    rep_gbs = rep_bytes / (rep_ms * 1e-3) / 1e9
+    del ws, next_in, next_out, prev, keys_d
+    return {
+        "float32_keys": {"workload": "single list n=%d binary32 keys, log-uniform magnitudes of "
+                                     "both signs, 25%% repeats, K=%d" % (n, K),
+                         "ms": round(sort_ms, 4), "Mnodes_per_s": round(n / (sort_ms * 1e-3) / 1e6, 1),
+                         "correct": ok_sort},
+        "repair_prev": {"workload": "backward links of the sorted %d-node list" % n,
+                        "ms": round(rep_ms, 4), "bytes_per_node": 8,
+                        "achieved_GBs": round(rep_gbs, 1),
+                        "frac": round(rep_gbs / bytemodel.MI355X_HBM_PEAK_GBS, 4),
+                        "correct": ok_prev},
     }
 
 
@@ -412,6 +481,11 @@ def main():
     r = run_plain(args, lib, torch, np, inputs, bytemodel, EventPool)
     torch.cuda.empty_cache()
 
+    extras = None
+    if not args.no_extras:
+        extras = run_extras(args, lib, torch, np, inputs, bytemodel)
+        torch.cuda.empty_cache()
+
     batched = None
     if args.c4 != "none":
         batched = run_batched(args, lib, torch, np, inputs, EventPool)
@@ -470,6 +544,7 @@ def main():
         "stages_ms": {k: round(v, 4) for k, v in sorted(r["stage_ms"].items(), key=lambda x: -x[1])},
         "stage_launches": r["launches"],
         "correct": r["correct"],
+        "extras": extras,
         "batched": batched,
         "served": served,
         "source_hash": r["src_hash"],

@@ -27,8 +27,17 @@ template <typename KeyT> __device__ __forceinline__ KeyT entry_key(const Entry<K
 template <typename KeyT> struct SegLen { static constexpr uint32_t value = sizeof(KeyT) == 8 ? 16 : 32; };
 
 // Digit-pass tile: kPassBlock threads x PassItems items.
-constexpr int kPassBlock = 512;
+constexpr int kPassBlock = 1024;
 template <typename KeyT> struct PassItems { static constexpr int value = sizeof(KeyT) == 8 ? 8 : 16; };
+// Consecutive tiles given to one XCD in a row.  Work-groups go to the 8 XCDs
+// round-robin by block index, so block b takes tile
+//   (q / C) * 8C + (b % 8) * C + q % C,  q = b / 8, C = kPassChunk:
+// each XCD then writes C neighbouring tiles' runs of every digit, and the
+// partial cache lines where two tiles' runs meet merge in that XCD's L2
+// instead of being written back twice.  The look-back still follows tile
+// order; the tile a chunk's first tile waits on starts 8(C-1) blocks later,
+// well inside the blocks the chip holds at once.
+constexpr uint32_t kPassChunk = 8;
 
 __device__ __forceinline__ void set_error(int32_t* status, int32_t code)
 {
@@ -401,7 +410,11 @@ __global__ __launch_bounds__(BLOCK, 4) void k_digit_pass(uint32_t pass, uint32_t
     for (uint32_t i = tid; i < WAVES * RADIX; i += BLOCK)
         (&s_wave[0][0])[i] = 0;
     __syncthreads();
-    const uint32_t tile = blockIdx.x;
+    const uint32_t q = blockIdx.x / 8u;
+    const uint32_t tile = (q / kPassChunk) * (8u * kPassChunk) + (blockIdx.x % 8u) * kPassChunk +
+                          q % kPassChunk;
+    if ((uint64_t)tile * TILE >= (uint64_t)n)
+        return;  // the grid is rounded up to whole chunk groups
     const uint64_t tbase = (uint64_t)tile * TILE;
     const uint64_t wbase = tbase + (uint64_t)wave * (64 * ITEMS);
 

@@ -77,18 +77,20 @@ static hipError_t launch_passes_rb(const Plan& P, char* ws, hipStream_t s, Prof*
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
+    const uint32_t group = 8u * kPassChunk;
+    const uint32_t grid = (uint32_t)((P.tiles + group - 1) / group * group);
     for (uint32_t p = 0; p < P.passes; p++) {
         LW* look = (LW*)(ws + P.o_look) + (size_t)p * P.tiles * RADIX;
         const uint32_t* dbase = (const uint32_t*)(ws + P.o_dbase) + (size_t)p * RADIX;
         mark(prof, s, kStagePass);
         if (p < P.key_passes) {
-            hipLaunchKernelGGL((k_digit_pass<KeyT, RB, BLOCK, ITEMS, LW, false>), dim3(P.tiles),
+            hipLaunchKernelGGL((k_digit_pass<KeyT, RB, BLOCK, ITEMS, LW, false>), dim3(grid),
                                dim3(BLOCK), 0, s, p, p * RB, (uint32_t)P.n, (KeyT*)(ws + P.o_keysA),
                                (uint32_t*)(ws + P.o_idxA), (KeyT*)(ws + P.o_keysB),
                                (uint32_t*)(ws + P.o_idxB), dbase, look, (Header*)(ws + P.o_header),
                                lm);
         } else {
-            hipLaunchKernelGGL((k_digit_pass<KeyT, RB, BLOCK, ITEMS, LW, true>), dim3(P.tiles),
+            hipLaunchKernelGGL((k_digit_pass<KeyT, RB, BLOCK, ITEMS, LW, true>), dim3(grid),
                                dim3(BLOCK), 0, s, p, (p - P.key_passes) * RB, (uint32_t)P.n,
                                (KeyT*)(ws + P.o_keysA), (uint32_t*)(ws + P.o_idxA),
                                (KeyT*)(ws + P.o_keysB), (uint32_t*)(ws + P.o_idxB), dbase, look,
