@@ -29,6 +29,7 @@ static uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
 static size_t entry_bytes(uint32_t key_bytes) { return key_bytes == 8 ? 16 : 8; }
 static size_t node_bytes(uint32_t key_bytes) { return key_bytes == 8 ? 16 : 8; }
+static size_t pair_bytes(uint32_t key_bytes) { return key_bytes == 8 ? 12 : 8; }
 // Entries a level-0 walker keeps in registers (matches the device SegLen).
 static uint32_t reg_entries(uint32_t key_bytes) { return key_bytes == 8 ? 16 : 32; }
 
@@ -65,7 +66,6 @@ static bool plan_common(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, uint
     P->flags = flags;
     P->key_bytes = M / 8;
     P->tile = pass_tile(P->key_bytes);
-    P->items = P->tile / 512;
     P->tiles = (uint32_t)ceil_div(n ? n : 1, P->tile);
     off = 0;
     P->o_header = off;
@@ -79,12 +79,12 @@ static bool plan_common(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, uint
     P->zero_end = off;
     P->o_nodes = off;
     off = align_up(off + n * node_bytes(P->key_bytes));
-    P->o_keysA = off;
-    off = align_up(off + n * P->key_bytes);
+    P->o_pairsA = off;
+    off = align_up(off + n * pair_bytes(P->key_bytes));
+    P->o_pairsB = off;
+    off = align_up(off + n * pair_bytes(P->key_bytes));
     P->o_idxA = off;
     off = align_up(off + n * 4);
-    P->o_keysB = off;
-    off = align_up(off + n * P->key_bytes);
     P->o_idxB = off;
     off = align_up(off + n * 4);
     LevelPlan& L = P->lv[0];

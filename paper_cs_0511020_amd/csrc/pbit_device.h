@@ -23,6 +23,51 @@ template <> struct __attribute__((aligned(16))) Entry<uint64_t> { uint64_t key; 
 
 template <typename KeyT> __device__ __forceinline__ KeyT entry_key(const Entry<KeyT>& e) { return (KeyT)e.key; }
 
+// (key, node) pair of the list-order buffers the digit passes stream through:
+// one 8-byte (16-byte for 64-bit keys) record per element, so a pass reads and
+// writes one contiguous run per digit instead of two half-length runs.
+// Narrow keys widen to 32 bits; a 64-bit key is kept as two words, so its
+// pair is 12 bytes (three-word loads and stores) rather than a padded 16.
+template <typename KeyT> struct __attribute__((aligned(8))) Pair { uint32_t key; uint32_t idx; };
+template <> struct Pair<uint64_t> { uint32_t klo; uint32_t khi; uint32_t idx; };
+
+template <typename KeyT> __device__ __forceinline__ Pair<KeyT> make_pair_kv(KeyT k, uint32_t i)
+{
+    Pair<KeyT> p;
+    if constexpr (sizeof(KeyT) == 8) {
+        p.klo = (uint32_t)k;
+        p.khi = (uint32_t)((uint64_t)k >> 32);
+    } else {
+        p.key = k;
+    }
+    p.idx = i;
+    return p;
+}
+
+template <typename KeyT> __device__ __forceinline__ KeyT pair_key(const Pair<KeyT>& p)
+{
+    if constexpr (sizeof(KeyT) == 8)
+        return ((uint64_t)p.khi << 32) | p.klo;
+    else
+        return (KeyT)p.key;
+}
+
+// Where the sorted order ends up: the idx field of pairs A, or an index buffer.
+struct OrderSrc {
+    const uint32_t* pair_idx;  // &pairsA[0].idx
+    uint32_t pair_words;       // pair stride in 32-bit words
+    const uint32_t* idxA;
+    const uint32_t* idxB;
+};
+__device__ __forceinline__ uint32_t order_at(const OrderSrc& o, uint32_t kind, uint64_t j)
+{
+    if (kind == kBufIdxA)
+        return o.idxA[j];
+    if (kind == kBufIdxB)
+        return o.idxB[j];
+    return o.pair_idx[j * o.pair_words];
+}
+
 // Entries of a level-0 chain kept in registers by its walker.
 template <typename KeyT> struct SegLen { static constexpr uint32_t value = sizeof(KeyT) == 8 ? 16 : 32; };
 
@@ -234,8 +279,7 @@ __global__ __launch_bounds__(256) void k_unchain(const uint2* __restrict__ chain
                                                  const Entry<KeyT>* __restrict__ ent,
                                                  uint32_t n_chains, uint32_t cap,
                                                  const uint32_t* __restrict__ offn_chain, uint32_t n,
-                                                 KeyT* __restrict__ keys_l,
-                                                 uint32_t* __restrict__ idx_l, Header* hdr)
+                                                 Pair<KeyT>* __restrict__ out, Header* hdr)
 {
     constexpr uint32_t G = 16;  // threads per chain
     if (hdr->status != 0)
@@ -252,8 +296,7 @@ __global__ __launch_bounds__(256) void k_unchain(const uint2* __restrict__ chain
         if (pos >= n)
             break;
         const Entry<KeyT> e = b[t];
-        keys_l[pos] = entry_key<KeyT>(e);
-        idx_l[pos] = e.idx;
+        out[pos] = make_pair_kv<KeyT>(entry_key<KeyT>(e), e.idx);
     }
 }
 
@@ -265,8 +308,7 @@ __global__ __launch_bounds__(256) void k_walk2(const NodeRec<KeyT>* __restrict__
                                                const uint32_t* __restrict__ resume,
                                                uint32_t n_chains, uint32_t cap,
                                                const uint32_t* __restrict__ offn_chain, uint32_t n,
-                                               KeyT* __restrict__ keys_l,
-                                               uint32_t* __restrict__ idx_l, Header* hdr)
+                                               Pair<KeyT>* __restrict__ out, Header* hdr)
 {
     if (hdr->status != 0)
         return;
@@ -281,8 +323,7 @@ __global__ __launch_bounds__(256) void k_walk2(const NodeRec<KeyT>* __restrict__
     const uint32_t end = (uint32_t)min<uint64_t>((uint64_t)offn_chain[c] + len, (uint64_t)n);
     while (pos < end && cur < n) {
         const NodeRec<KeyT> r = nodes[cur];
-        keys_l[pos] = (KeyT)r.key;
-        idx_l[pos] = cur;
+        out[pos] = make_pair_kv<KeyT>((KeyT)r.key, cur);
         pos++;
         cur = r.next;
     }
@@ -327,22 +368,30 @@ __global__ __launch_bounds__(256) void k_schedule(const uint32_t* __restrict__ h
         __syncthreads();
     }
     if (tid == 0) {
+        // The list order starts as pairs A.  Key passes go pairs to pairs, the
+        // last one that runs to index buffer A; list-id passes go index buffer
+        // to index buffer (or from pairs A when every key pass was skipped).
         int last_key = -1;
         for (uint32_t p = 0; p < key_passes; p++)
             if (!s_skip[p])
                 last_key = (int)p;
-        uint32_t cur = 0;
+        uint32_t cur = kBufPairsA;
         for (uint32_t p = 0; p < passes; p++) {
             PassSched ps;
             ps.skip = s_skip[p];
-            ps.in_buf = cur;
-            ps.write_keys = (int)p < last_key ? 1u : 0u;
+            ps.in_kind = cur;
             ps.pad = 0;
+            if (p < key_passes)
+                ps.out_kind = (int)p == last_key ? (uint32_t)kBufIdxA
+                                                 : (cur == kBufPairsA ? (uint32_t)kBufPairsB
+                                                                      : (uint32_t)kBufPairsA);
+            else
+                ps.out_kind = cur == kBufIdxA ? (uint32_t)kBufIdxB : (uint32_t)kBufIdxA;
             if (!ps.skip)
-                cur ^= 1u;
+                cur = ps.out_kind;
             hdr->sched[p] = ps;
         }
-        hdr->final_buf = cur;
+        hdr->final_kind = cur;
     }
 }
 
@@ -376,9 +425,9 @@ constexpr uint32_t kSpinLimit = 4096;
 
 template <typename KeyT, int RB, int BLOCK, int ITEMS, typename LW, bool LID>
 __global__ __launch_bounds__(BLOCK, 4) void k_digit_pass(uint32_t pass, uint32_t shift, uint32_t n,
-                                                         KeyT* __restrict__ keysA,
+                                                         Pair<KeyT>* __restrict__ pairsA,
+                                                         Pair<KeyT>* __restrict__ pairsB,
                                                          uint32_t* __restrict__ idxA,
-                                                         KeyT* __restrict__ keysB,
                                                          uint32_t* __restrict__ idxB,
                                                          const uint32_t* __restrict__ dbase,
                                                          LW* __restrict__ look, Header* hdr,
@@ -400,10 +449,15 @@ __global__ __launch_bounds__(BLOCK, 4) void k_digit_pass(uint32_t pass, uint32_t
     const PassSched ps = hdr->sched[pass];
     if (ps.skip)
         return;
-    const KeyT* kin = ps.in_buf ? keysB : keysA;
-    const uint32_t* iin = ps.in_buf ? idxB : idxA;
-    KeyT* kout = ps.in_buf ? keysA : keysB;
-    uint32_t* iout = ps.in_buf ? idxA : idxB;
+    // key passes read pairs; list-id passes read indices (or pairs A's idx
+    // field when every key pass was skipped); only key passes before the last
+    // one write pairs
+    const bool in_pairs = ps.in_kind < kBufIdxA;
+    const bool out_pairs = ps.out_kind < kBufIdxA;
+    const Pair<KeyT>* pin = ps.in_kind == kBufPairsB ? pairsB : pairsA;
+    const uint32_t* iin = ps.in_kind == kBufIdxB ? idxB : idxA;
+    Pair<KeyT>* pout = ps.out_kind == kBufPairsB ? pairsB : pairsA;
+    uint32_t* iout = ps.out_kind == kBufIdxB ? idxB : idxA;
 
     const uint32_t tid = threadIdx.x;
     const uint32_t wave = tid / 64, lane = tid % 64;
@@ -424,11 +478,14 @@ __global__ __launch_bounds__(BLOCK, 4) void k_digit_pass(uint32_t pass, uint32_t
     for (int i = 0; i < ITEMS; i++) {
         const uint64_t e = wbase + (uint64_t)i * 64 + lane;
         if (e < n) {
-            idx[i] = iin[e];
-            if constexpr (LID)
+            if constexpr (LID) {
+                idx[i] = in_pairs ? pin[e].idx : iin[e];
                 key[i] = list_of(lm, idx[i]);
-            else
-                key[i] = kin[e];
+            } else {
+                const Pair<KeyT> v = pin[e];
+                key[i] = (SKey)pair_key<KeyT>(v);
+                idx[i] = v.idx;
+            }
             dig[i] = (uint32_t)(key[i] >> shift) & (RADIX - 1u);
         } else {
             key[i] = 0;
@@ -526,9 +583,9 @@ __global__ __launch_bounds__(BLOCK, 4) void k_digit_pass(uint32_t pass, uint32_t
                     for (uint64_t q = b0; q < b1; q++) {
                         uint32_t x;
                         if constexpr (LID)
-                            x = list_of(lm, iin[q]);
+                            x = list_of(lm, in_pairs ? pin[q].idx : iin[q]);
                         else
-                            x = (uint32_t)(kin[q] >> shift);
+                            x = (uint32_t)(pair_key<KeyT>(pin[q]) >> shift);
                         if constexpr (LID)
                             x >>= shift;
                         c += (x & (RADIX - 1u)) == d;
@@ -570,11 +627,10 @@ __global__ __launch_bounds__(BLOCK, 4) void k_digit_pass(uint32_t pass, uint32_t
             const uint32_t d = (uint32_t)(kv.key >> shift) & (RADIX - 1u);
             const uint32_t g = j + s_delta[d];
             if (g < n) {
-                if constexpr (!LID) {
-                    if (ps.write_keys)
-                        kout[g] = kv.key;
-                }
-                iout[g] = kv.idx;
+                if (!LID && out_pairs)
+                    pout[g] = make_pair_kv<KeyT>((KeyT)kv.key, kv.idx);
+                else
+                    iout[g] = kv.idx;
             }
         }
     }

@@ -292,8 +292,7 @@ __global__ __launch_bounds__(256) void k_fdown(const uint2* __restrict__ recs, u
 // next_out[order[j]] = order[j+1] inside each list's run, NIL at its end;
 // the first node of each run is the list's new head.  In the gather form the
 // result goes to each list's own array in list-local indices.
-__global__ __launch_bounds__(256) void k_frelink(const uint32_t* __restrict__ idxA,
-                                                 const uint32_t* __restrict__ idxB, ForestArgs F,
+__global__ __launch_bounds__(256) void k_frelink(OrderSrc src, ForestArgs F,
                                                  uint32_t* __restrict__ next_out,
                                                  uint32_t* __restrict__ new_heads,
                                                  int32_t* __restrict__ d_status, const Header* hdr)
@@ -308,11 +307,11 @@ __global__ __launch_bounds__(256) void k_frelink(const uint32_t* __restrict__ id
         new_heads[j] = kNil;
     if (j >= F.n)
         return;
-    const uint32_t* order = hdr->final_buf ? idxB : idxA;
+    const uint32_t kind = hdr->final_kind;
     const uint32_t l = list_of(F.lm, j);
     const uint64_t lo = F.offsets[l], hi = F.offsets[l + 1];
-    const uint32_t node = order[j];
-    const uint32_t succ = (j + 1 < hi) ? order[j + 1] : kNil;
+    const uint32_t node = order_at(src, kind, j);
+    const uint32_t succ = (j + 1 < hi) ? order_at(src, kind, j + 1) : kNil;
     if (node < lo || node >= hi)
         return;  // cannot happen for a sorted batch; keeps every write in bounds
     if (F.next_out_ptrs) {
@@ -468,9 +467,9 @@ hipError_t enqueue_sort_lists(const Plan& P, const uint32_t* heads, const uint64
     {
         const uint64_t threads = P.n > P.num_lists ? P.n : P.num_lists;
         mark(prof, s, kStageRelink);
+        const OrderSrc src = P.key_bytes == 8 ? order_src<uint64_t>(P, ws) : order_src<uint32_t>(P, ws);
         hipLaunchKernelGGL(k_frelink, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s,
-                           (const uint32_t*)(ws + P.o_idxA), (const uint32_t*)(ws + P.o_idxB), F,
-                           next_out, new_heads, d_status, (const Header*)hdr);
+                           src, F, next_out, new_heads, d_status, (const Header*)hdr);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }

@@ -22,17 +22,21 @@ constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagPrefix = 2u << 30;
 constexpr uint32_t kCountMask = (1u << 30) - 1u;
 
+// List-order buffers: (key, node) pairs while key passes remain, node
+// indices alone after the last key pass.
+enum BufKind : uint32_t { kBufPairsA = 0, kBufPairsB = 1, kBufIdxA = 2, kBufIdxB = 3 };
+
 struct PassSched {
-    uint32_t skip;        // every element has the same digit: the pass is the identity
-    uint32_t in_buf;      // 0: buffer A, 1: buffer B
-    uint32_t write_keys;  // a later key pass still reads the keys
+    uint32_t skip;      // every element has the same digit: the pass is the identity
+    uint32_t in_kind;   // BufKind read
+    uint32_t out_kind;  // BufKind written
     uint32_t pad;
 };
 
 // Device-side header at the start of the workspace (zeroed per sort).
 struct Header {
     int32_t status;
-    uint32_t final_buf;
+    uint32_t final_kind;      // BufKind holding the sorted order
     uint32_t nil_count;       // next[] entries equal to NIL
     uint32_t expect_nil;      // many-list sorts: non-empty lists (one NIL each)
     uint64_t hsum[2];         // sum of h(next) over non-NIL next[] minus sum of h(i)
@@ -68,14 +72,14 @@ struct Prof {
 struct Plan {
     uint64_t n;
     uint32_t M, K, RB, radix, passes, flags, key_bytes;
-    uint32_t tile, tiles, items;
+    uint32_t tile, tiles;
     uint32_t key_passes;  // passes on key patterns; the rest split on list ids
     uint32_t num_lists;   // many-list sorts
     uint32_t log_block;   // many-list sorts: node block size of the list table
     int levels;           // walk levels; the base ranks level `levels`
     LevelPlan lv[kMaxLevels];
     size_t o_header, o_hist, o_dbase, o_look, zero_end;
-    size_t o_nodes, o_keysA, o_idxA, o_keysB, o_idxB;
+    size_t o_nodes, o_pairsA, o_pairsB, o_idxA, o_idxB;
     size_t o_table, o_headbits;  // many-list sorts
     size_t total;
 };

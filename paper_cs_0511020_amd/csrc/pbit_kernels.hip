@@ -299,8 +299,7 @@ __global__ __launch_bounds__(256) void k_down(const uint2* __restrict__ recs, ui
 
 // ---------------------------------------------------------------- relink
 // next[order[j]] = order[j+1]; the last node gets NIL; result = {head, status}.
-__global__ __launch_bounds__(256) void k_relink(const uint32_t* __restrict__ idxA,
-                                                const uint32_t* __restrict__ idxB, uint32_t n,
+__global__ __launch_bounds__(256) void k_relink(OrderSrc src, uint32_t n,
                                                 uint32_t* __restrict__ next_out,
                                                 uint32_t* __restrict__ result, const Header* hdr)
 {
@@ -313,10 +312,10 @@ __global__ __launch_bounds__(256) void k_relink(const uint32_t* __restrict__ idx
         }
         return;
     }
-    const uint32_t* order = hdr->final_buf ? idxB : idxA;
+    const uint32_t kind = hdr->final_kind;
     if (j < n) {
-        const uint32_t node = order[j];
-        const uint32_t succ = (j + 1 < n) ? order[j + 1] : kNil;
+        const uint32_t node = order_at(src, kind, j);
+        const uint32_t succ = (j + 1 < n) ? order_at(src, kind, j + 1) : kNil;
         if (node < n)
             next_out[node] = succ;
         if (j == 0) {
@@ -423,9 +422,9 @@ hipError_t enqueue_sort(const Plan& P, uint32_t head, const uint32_t* next_in, u
     {
         uint32_t blocks = (uint32_t)((P.n + 255) / 256);
         mark(prof, s, kStageRelink);
-        hipLaunchKernelGGL(k_relink, dim3(blocks), dim3(256), 0, s,
-                           (const uint32_t*)(ws + P.o_idxA), (const uint32_t*)(ws + P.o_idxB),
-                           (uint32_t)P.n, next_out, d_result, (const Header*)hdr);
+        const OrderSrc src = P.key_bytes == 8 ? order_src<uint64_t>(P, ws) : order_src<uint32_t>(P, ws);
+        hipLaunchKernelGGL(k_relink, dim3(blocks), dim3(256), 0, s, src, (uint32_t)P.n, next_out,
+                           d_result, (const Header*)hdr);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }

@@ -85,15 +85,15 @@ static hipError_t launch_passes_rb(const Plan& P, char* ws, hipStream_t s, Prof*
         mark(prof, s, kStagePass);
         if (p < P.key_passes) {
             hipLaunchKernelGGL((k_digit_pass<KeyT, RB, BLOCK, ITEMS, LW, false>), dim3(grid),
-                               dim3(BLOCK), 0, s, p, p * RB, (uint32_t)P.n, (KeyT*)(ws + P.o_keysA),
-                               (uint32_t*)(ws + P.o_idxA), (KeyT*)(ws + P.o_keysB),
-                               (uint32_t*)(ws + P.o_idxB), dbase, look, (Header*)(ws + P.o_header),
-                               lm);
+                               dim3(BLOCK), 0, s, p, p * RB, (uint32_t)P.n,
+                               (Pair<KeyT>*)(ws + P.o_pairsA), (Pair<KeyT>*)(ws + P.o_pairsB),
+                               (uint32_t*)(ws + P.o_idxA), (uint32_t*)(ws + P.o_idxB), dbase, look,
+                               (Header*)(ws + P.o_header), lm);
         } else {
             hipLaunchKernelGGL((k_digit_pass<KeyT, RB, BLOCK, ITEMS, LW, true>), dim3(grid),
                                dim3(BLOCK), 0, s, p, (p - P.key_passes) * RB, (uint32_t)P.n,
-                               (KeyT*)(ws + P.o_keysA), (uint32_t*)(ws + P.o_idxA),
-                               (KeyT*)(ws + P.o_keysB), (uint32_t*)(ws + P.o_idxB), dbase, look,
+                               (Pair<KeyT>*)(ws + P.o_pairsA), (Pair<KeyT>*)(ws + P.o_pairsB),
+                               (uint32_t*)(ws + P.o_idxA), (uint32_t*)(ws + P.o_idxB), dbase, look,
                                (Header*)(ws + P.o_header), lm);
         }
         e = hipGetLastError();
@@ -116,6 +116,14 @@ static hipError_t launch_passes(const Plan& P, char* ws, hipStream_t s, Prof* pr
 }
 
 // Level-0 chains (lv[0]) to list order: stored entries, then re-walked rests.
+template <typename KeyT> static OrderSrc order_src(const Plan& P, char* ws)
+{
+    constexpr uint32_t words = sizeof(Pair<KeyT>) / 4;
+    static_assert(sizeof(Pair<KeyT>) == (sizeof(KeyT) == 8 ? 12 : 8), "pair layout");
+    return OrderSrc{(const uint32_t*)(ws + P.o_pairsA) + (sizeof(KeyT) == 8 ? 2 : 1), words,
+                    (const uint32_t*)(ws + P.o_idxA), (const uint32_t*)(ws + P.o_idxB)};
+}
+
 template <typename KeyT>
 static hipError_t launch_unchain(const Plan& P, char* ws, hipStream_t s, Prof* prof)
 {
@@ -125,8 +133,7 @@ static hipError_t launch_unchain(const Plan& P, char* ws, hipStream_t s, Prof* p
     hipLaunchKernelGGL((k_unchain<KeyT>), dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s,
                        (const uint2*)(ws + L.o_chain_rec), (const Entry<KeyT>*)(ws + L.o_ent),
                        (uint32_t)L.n_static, L.cap, (const uint32_t*)(ws + L.o_offn),
-                       (uint32_t)P.n, (KeyT*)(ws + P.o_keysA), (uint32_t*)(ws + P.o_idxA),
-                       (Header*)(ws + P.o_header));
+                       (uint32_t)P.n, (Pair<KeyT>*)(ws + P.o_pairsA), (Header*)(ws + P.o_header));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
@@ -134,8 +141,8 @@ static hipError_t launch_unchain(const Plan& P, char* ws, hipStream_t s, Prof* p
     hipLaunchKernelGGL((k_walk2<KeyT>), dim3((uint32_t)((L.n_static + 255) / 256)), dim3(256), 0, s,
                        (const NodeRec<KeyT>*)(ws + P.o_nodes), (const uint2*)(ws + L.o_chain_rec),
                        (const uint32_t*)(ws + L.o_resume), (uint32_t)L.n_static, L.cap,
-                       (const uint32_t*)(ws + L.o_offn), (uint32_t)P.n, (KeyT*)(ws + P.o_keysA),
-                       (uint32_t*)(ws + P.o_idxA), (Header*)(ws + P.o_header));
+                       (const uint32_t*)(ws + L.o_offn), (uint32_t)P.n,
+                       (Pair<KeyT>*)(ws + P.o_pairsA), (Header*)(ws + P.o_header));
     return hipGetLastError();
 }
 
