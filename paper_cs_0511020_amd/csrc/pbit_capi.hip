@@ -98,6 +98,8 @@ static bool plan_common(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, uint
     off = align_up(off + L.n_static * cap * entry_bytes(P->key_bytes));
     L.o_resume = off;
     off = align_up(off + L.n_static * 4);
+    L.o_long = off;
+    off = align_up(off + L.n_static * 4);
     L.o_offn = off;
     off = align_up(off + L.n_static * 4);
     return true;

@@ -273,18 +273,47 @@ __global__ __launch_bounds__(256) void k_pack(Src src, uint32_t n, KeyT float_se
 }
 
 // ---------------------------------------------------------------- unchain
-// The stored entries of every level-0 chain (up to `cap`) to list order.
+// Every level-0 chain to list order: its stored entries (up to `cap`) are
+// copied to its place, 16 threads per chain.  The first kLongBlocks blocks
+// instead take the chains longer than their slot (listed by the walk) and
+// walk their rests again from the resume node, writing straight to list
+// order; being dispatched first, that latency-bound tail overlaps the copy.
+constexpr uint32_t kLongBlocks = 16;
+
 template <typename KeyT>
 __global__ __launch_bounds__(256) void k_unchain(const uint2* __restrict__ chain_rec,
                                                  const Entry<KeyT>* __restrict__ ent,
                                                  uint32_t n_chains, uint32_t cap,
                                                  const uint32_t* __restrict__ offn_chain, uint32_t n,
+                                                 const NodeRec<KeyT>* __restrict__ nodes,
+                                                 const uint32_t* __restrict__ resume,
+                                                 const uint32_t* __restrict__ long_list,
                                                  Pair<KeyT>* __restrict__ out, Header* hdr)
 {
     constexpr uint32_t G = 16;  // threads per chain
     if (hdr->status != 0)
         return;
-    const uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (blockIdx.x < kLongBlocks) {
+        const uint32_t n_long = hdr->n_long;
+        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_long;
+             i += kLongBlocks * blockDim.x) {
+            const uint32_t c = long_list[i];
+            if (c >= n_chains)
+                continue;
+            const uint32_t len = chain_rec[c].y;
+            uint32_t cur = resume[c];
+            uint32_t pos = offn_chain[c] + cap;
+            const uint32_t end = (uint32_t)min<uint64_t>((uint64_t)offn_chain[c] + len, (uint64_t)n);
+            while (pos < end && cur < n) {
+                const NodeRec<KeyT> r = nodes[cur];
+                out[pos] = make_pair_kv<KeyT>((KeyT)r.key, cur);
+                pos++;
+                cur = r.next;
+            }
+        }
+        return;
+    }
+    const uint64_t g = (blockIdx.x - kLongBlocks) * (uint64_t)blockDim.x + threadIdx.x;
     const uint32_t c = (uint32_t)(g / G);
     if (c >= n_chains)
         return;
@@ -297,35 +326,6 @@ __global__ __launch_bounds__(256) void k_unchain(const uint2* __restrict__ chain
             break;
         const Entry<KeyT> e = b[t];
         out[pos] = make_pair_kv<KeyT>(entry_key<KeyT>(e), e.idx);
-    }
-}
-
-// The rest of every level-0 chain longer than its slot, walked again from
-// its resume node and written straight to list order.
-template <typename KeyT>
-__global__ __launch_bounds__(256) void k_walk2(const NodeRec<KeyT>* __restrict__ nodes,
-                                               const uint2* __restrict__ chain_rec,
-                                               const uint32_t* __restrict__ resume,
-                                               uint32_t n_chains, uint32_t cap,
-                                               const uint32_t* __restrict__ offn_chain, uint32_t n,
-                                               Pair<KeyT>* __restrict__ out, Header* hdr)
-{
-    if (hdr->status != 0)
-        return;
-    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_chains)
-        return;
-    const uint32_t len = chain_rec[c].y;
-    if (len <= cap)
-        return;
-    uint32_t cur = resume[c];
-    uint32_t pos = offn_chain[c] + cap;
-    const uint32_t end = (uint32_t)min<uint64_t>((uint64_t)offn_chain[c] + len, (uint64_t)n);
-    while (pos < end && cur < n) {
-        const NodeRec<KeyT> r = nodes[cur];
-        out[pos] = make_pair_kv<KeyT>((KeyT)r.key, cur);
-        pos++;
-        cur = r.next;
     }
 }
 

@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void k_fwalk0(const NodeRec<KeyT>* __restrict_
                                                 uint2* __restrict__ chain_rec,
                                                 Entry<KeyT>* __restrict__ ent,
                                                 uint32_t* __restrict__ resume, uint32_t cap,
-                                                Header* hdr)
+                                                uint32_t* __restrict__ long_list, Header* hdr)
 {
     constexpr uint32_t C = SegLen<KeyT>::value;
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -184,6 +184,8 @@ __global__ __launch_bounds__(256) void k_fwalk0(const NodeRec<KeyT>* __restrict_
         if (t < len && t < cap)
             b[t] = e[t];
     resume[c] = rest_from;
+    if (len > cap)
+        long_list[atomicAdd(&hdr->n_long, 1u)] = c;
     chain_rec[c] = make_uint2(nx == kNil ? kNil : F.H + (nx >> kLog0), len);
 }
 
@@ -343,7 +345,8 @@ static hipError_t launch_fwalk0(const Plan& P, const ForestArgs& F, char* ws, hi
     hipLaunchKernelGGL((k_fwalk0<KeyT>), dim3((uint32_t)((L.n_static + 255) / 256)), dim3(256), 0,
                        s, (const NodeRec<KeyT>*)(ws + P.o_nodes), F, (uint32_t)L.n_static,
                        (uint2*)(ws + L.o_chain_rec), (Entry<KeyT>*)(ws + L.o_ent),
-                       (uint32_t*)(ws + L.o_resume), L.cap, (Header*)(ws + P.o_header));
+                       (uint32_t*)(ws + L.o_resume), L.cap, (uint32_t*)(ws + L.o_long),
+                       (Header*)(ws + P.o_header));
     return hipGetLastError();
 }
 

@@ -39,6 +39,8 @@ struct Header {
     uint32_t final_kind;      // BufKind holding the sorted order
     uint32_t nil_count;       // next[] entries equal to NIL
     uint32_t expect_nil;      // many-list sorts: non-empty lists (one NIL each)
+    uint32_t n_long;          // level-0 chains longer than their slot
+    uint32_t pad0;
     uint64_t hsum[2];         // sum of h(next) over non-NIL next[] minus sum of h(i)
     PassSched sched[kMaxPasses];
 };
@@ -50,6 +52,7 @@ struct LevelPlan {
     size_t o_chain_rec;   // uint2 {successor chain, weight} per chain
     size_t o_ent;         // level 0: stored head entries of every chain
     size_t o_resume;      // level 0: node where the unstored rest of a chain starts
+    size_t o_long;        // level 0: ids of the chains longer than `cap` (Header::n_long)
     uint32_t cap;         // level 0: entries stored per chain
     size_t o_offn;        // u32 offset (in nodes) of every chain
 };
@@ -57,7 +60,9 @@ struct LevelPlan {
 // Stages of one sort, in launch order (measurement hooks name them).
 enum Stage : int32_t {
     kStageZero = 0, kStagePack, kStageWalk0, kStageWalkUp, kStageBase, kStageDown,
-    kStageUnchain, kStageSchedule, kStagePass, kStageRelink, kStageWalk2, kStageCount
+    kStageUnchain, kStageSchedule, kStagePass, kStageRelink,
+    kStageWalk2,  // no longer a launch of its own: the long rests run inside unchain
+    kStageCount
 };
 
 // Optional event recording between stages: events[i] is recorded before the

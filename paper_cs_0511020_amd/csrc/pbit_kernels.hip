@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256) void k_walk0(const NodeRec<KeyT>* __restrict__
                                                uint2* __restrict__ chain_rec,
                                                Entry<KeyT>* __restrict__ ent,
                                                uint32_t* __restrict__ resume, uint32_t cap,
-                                               Header* hdr)
+                                               uint32_t* __restrict__ long_list, Header* hdr)
 {
     constexpr uint32_t C = SegLen<KeyT>::value;
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -137,6 +137,8 @@ __global__ __launch_bounds__(256) void k_walk0(const NodeRec<KeyT>* __restrict__
         if (t < len && t < cap)
             b[t] = e[t];
     resume[c] = rest_from;
+    if (len > cap)
+        long_list[atomicAdd(&hdr->n_long, 1u)] = c;
     const uint32_t succ = (nx == kNil) ? kNil : (nx == head ? 0u : 1u + (nx >> kLog0));
     chain_rec[c] = make_uint2(succ, len);
 }
@@ -340,7 +342,7 @@ static hipError_t launch_walk0(const Plan& P, uint32_t head, char* ws, hipStream
                        s, (const NodeRec<KeyT>*)(ws + P.o_nodes), (uint32_t)P.n, head,
                        (uint32_t)L.n_static, (uint2*)(ws + L.o_chain_rec),
                        (Entry<KeyT>*)(ws + L.o_ent), (uint32_t*)(ws + L.o_resume), L.cap,
-                       (Header*)(ws + P.o_header));
+                       (uint32_t*)(ws + L.o_long), (Header*)(ws + P.o_header));
     return hipGetLastError();
 }
 

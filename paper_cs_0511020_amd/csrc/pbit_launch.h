@@ -115,7 +115,7 @@ static hipError_t launch_passes(const Plan& P, char* ws, hipStream_t s, Prof* pr
     }
 }
 
-// Level-0 chains (lv[0]) to list order: stored entries, then re-walked rests.
+// The buffers the relink may find the sorted order in.
 template <typename KeyT> static OrderSrc order_src(const Plan& P, char* ws)
 {
     constexpr uint32_t words = sizeof(Pair<KeyT>) / 4;
@@ -124,25 +124,20 @@ template <typename KeyT> static OrderSrc order_src(const Plan& P, char* ws)
                     (const uint32_t*)(ws + P.o_idxA), (const uint32_t*)(ws + P.o_idxB)};
 }
 
+// Level-0 chains (lv[0]) to list order: stored entries and re-walked rests.
 template <typename KeyT>
 static hipError_t launch_unchain(const Plan& P, char* ws, hipStream_t s, Prof* prof)
 {
     const LevelPlan& L = P.lv[0];
     const uint64_t threads = L.n_static * 16;
     mark(prof, s, kStageUnchain);
-    hipLaunchKernelGGL((k_unchain<KeyT>), dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s,
-                       (const uint2*)(ws + L.o_chain_rec), (const Entry<KeyT>*)(ws + L.o_ent),
-                       (uint32_t)L.n_static, L.cap, (const uint32_t*)(ws + L.o_offn),
-                       (uint32_t)P.n, (Pair<KeyT>*)(ws + P.o_pairsA), (Header*)(ws + P.o_header));
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
-        return e;
-    mark(prof, s, kStageWalk2);
-    hipLaunchKernelGGL((k_walk2<KeyT>), dim3((uint32_t)((L.n_static + 255) / 256)), dim3(256), 0, s,
-                       (const NodeRec<KeyT>*)(ws + P.o_nodes), (const uint2*)(ws + L.o_chain_rec),
-                       (const uint32_t*)(ws + L.o_resume), (uint32_t)L.n_static, L.cap,
+    hipLaunchKernelGGL((k_unchain<KeyT>), dim3(kLongBlocks + (uint32_t)((threads + 255) / 256)),
+                       dim3(256), 0, s, (const uint2*)(ws + L.o_chain_rec),
+                       (const Entry<KeyT>*)(ws + L.o_ent), (uint32_t)L.n_static, L.cap,
                        (const uint32_t*)(ws + L.o_offn), (uint32_t)P.n,
-                       (Pair<KeyT>*)(ws + P.o_pairsA), (Header*)(ws + P.o_header));
+                       (const NodeRec<KeyT>*)(ws + P.o_nodes), (const uint32_t*)(ws + L.o_resume),
+                       (const uint32_t*)(ws + L.o_long), (Pair<KeyT>*)(ws + P.o_pairsA),
+                       (Header*)(ws + P.o_header));
     return hipGetLastError();
 }
 

@@ -112,6 +112,27 @@ def test_many_lists_three_id_passes(oracle_mod):
     check(oracle_mod, heads, offs, nxt, keys, 8)
 
 
+def test_long_chains_in_batch(oracle_mod):
+    """Slabs whose level-0 chains exceed their stored slot."""
+    from .test_gpu_parity import long_chain_order
+    rng = inputs.rng_for(4300)
+    lengths = np.array([40000, 17, 0, 25000, 3000, 1], dtype=np.int64)
+    offs = np.zeros(len(lengths) + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum(lengths)
+    nxt = np.full(int(offs[-1]), NIL, dtype=np.uint32)
+    heads = np.full(len(lengths), NIL, dtype=np.uint32)
+    for l, ln in enumerate(lengths):
+        if ln == 0:
+            continue
+        lo = int(offs[l])
+        order = long_chain_order(int(ln), rng, max(1, int(ln) // 250)) + lo
+        nxt[order[:-1]] = order[1:]
+        heads[l] = order[0]
+    keys = inputs.uniform_keys(nxt.shape[0], 32, rng)
+    say("batched long chains")
+    check(oracle_mod, heads, offs, nxt, keys, 8)
+
+
 def test_batched_equals_alone():
     """Each list of a batch sorts exactly as the single-list entry point
     sorts it alone."""

@@ -146,6 +146,35 @@ def test_special_layouts(oracle_mod):
     run_parity(oracle_mod, head, nxt, keys, 4)
 
 
+def long_chain_order(n, rng, spread=200):
+    """A list order whose level-0 chains (runs between multiples of 16) are
+    far longer than a chain's stored slot: `spread` multiples of 16 spaced
+    evenly through the other nodes, the remaining multiples at the end."""
+    nodes = rng.permutation(n)
+    mult = nodes[nodes % 16 == 0]
+    rest = nodes[nodes % 16 != 0]
+    head_part = np.array_split(rest, spread)
+    out = []
+    for k, part in enumerate(head_part):
+        out.append(part)
+        if k < len(mult):
+            out.append(mult[k:k + 1])
+    out.append(mult[spread:])
+    return np.concatenate(out).astype(np.uint32)
+
+
+def test_long_chains(oracle_mod):
+    rng = inputs.rng_for(66)
+    for n, spread in [(50000, 200), (50000, 1), (300000, 600)]:
+        say("long chains n=%d spread=%d" % (n, spread))
+        order = long_chain_order(n, rng, spread)
+        nxt, head = inputs.links_from_order(order)
+        keys = inputs.uniform_keys(n, 32, rng)
+        keys[::7] = keys[3]
+        run_parity(oracle_mod, head, nxt, keys, 8)
+        run_parity(oracle_mod, head, nxt, keys.astype(np.uint64) * 3, 4)
+
+
 def test_malformed_lists_are_rejected_untouched():
     rng = inputs.rng_for(71)
     n = 30000
