@@ -274,11 +274,13 @@ __global__ __launch_bounds__(256) void k_pack(Src src, uint32_t n, KeyT float_se
 
 // ---------------------------------------------------------------- unchain
 // Every level-0 chain to list order: its stored entries (up to `cap`) are
-// copied to its place, 16 threads per chain.  The first kLongBlocks blocks
-// instead take the chains longer than their slot (listed by the walk) and
-// walk their rests again from the resume node, writing straight to list
-// order; being dispatched first, that latency-bound tail overlaps the copy.
+// copied to its place, 2^kLog0 threads (the mean chain length) per chain.
+// The first kLongBlocks blocks instead take the chains longer than their slot
+// (listed by the walk) and walk their rests again from the resume node,
+// writing straight to list order; being dispatched first, that latency-bound
+// tail overlaps the copy.
 constexpr uint32_t kLongBlocks = 16;
+constexpr uint32_t kUnchainThreads = 1u << kLog0;
 
 template <typename KeyT>
 __global__ __launch_bounds__(256) void k_unchain(const uint2* __restrict__ chain_rec,
@@ -290,7 +292,7 @@ __global__ __launch_bounds__(256) void k_unchain(const uint2* __restrict__ chain
                                                  const uint32_t* __restrict__ long_list,
                                                  Pair<KeyT>* __restrict__ out, Header* hdr)
 {
-    constexpr uint32_t G = 16;  // threads per chain
+    constexpr uint32_t G = kUnchainThreads;  // threads per chain (the mean chain length)
     if (hdr->status != 0)
         return;
     if (blockIdx.x < kLongBlocks) {

@@ -9,11 +9,20 @@ constexpr uint32_t kNil = 0xFFFFFFFFu;
 
 // Level 0 walks the node list; every node index that is a multiple of
 // 2^kLog0 (and the head) starts a chain.
-constexpr uint32_t kLog0 = 4;
+#ifndef PBIT_LOG0
+#define PBIT_LOG0 4
+#endif
+#ifndef PBIT_LOGUP
+#define PBIT_LOGUP 2
+#endif
+#ifndef PBIT_BASEMAX
+#define PBIT_BASEMAX 8192
+#endif
+constexpr uint32_t kLog0 = PBIT_LOG0;
 // Levels >= 1 walk the list of chains of the level below.
-constexpr uint32_t kLogUp = 3;
+constexpr uint32_t kLogUp = PBIT_LOGUP;
 // The last level is ranked inside one workgroup's LDS.
-constexpr uint32_t kBaseMax = 8192;
+constexpr uint32_t kBaseMax = PBIT_BASEMAX;
 constexpr int kMaxLevels = 12;
 constexpr int kMaxPasses = 96;
 
