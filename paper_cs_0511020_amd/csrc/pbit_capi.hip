@@ -33,6 +33,19 @@ static size_t pair_bytes(uint32_t key_bytes) { return key_bytes == 8 ? 12 : 8; }
 // Entries a level-0 walker keeps in registers (matches the device SegLen).
 static uint32_t reg_entries(uint32_t key_bytes) { return key_bytes == 8 ? 16 : 32; }
 
+// Entries stored per level-0 chain (a multiple of the walker's register
+// block).  Chain lengths are geometric with mean 16, so a slot of 128 leaves
+// about 1 chain in 4000 with a rest to re-walk and 64 about 1 in 60; the slots
+// cost 8 (16 for 64-bit keys) bytes per entry, so larger inputs get less.
+static uint32_t level0_cap(uint64_t n, uint32_t reg)
+{
+    if (n <= (1ull << 26))
+        return 128u;
+    if (n <= (1ull << 31))
+        return 64u > reg ? 64u : reg;
+    return reg;
+}
+
 // Pattern width when the caller leaves it to the library.
 static uint32_t default_k(uint32_t M) { return M == 8 ? 4u : 8u; }
 
@@ -99,7 +112,7 @@ static bool plan_common(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, uint
     L.o_resume = off;
     off = align_up(off + L.n_static * 4);
     L.o_long = off;
-    off = align_up(off + L.n_static * 4);
+    off = align_up(off + (size_t)2 * kLongListMax * 4);
     L.o_offn = off;
     off = align_up(off + L.n_static * 4);
     return true;
@@ -119,7 +132,7 @@ bool make_plan(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, Plan* P)
         return true;
     }
     const uint32_t reg = reg_entries(M / 8);
-    const uint32_t cap = n <= (1ull << 26) ? 128u : reg;
+    const uint32_t cap = level0_cap(n, reg);
     size_t off = 0;
     if (!plan_common(n, M, K, flags, 0, 4, 1 + ceil_div(n, 1ull << kLog0), cap, P, off))
         return false;
@@ -164,7 +177,7 @@ bool make_plan_lists(uint64_t n, uint32_t num_lists, uint32_t M, uint32_t K, uin
     const uint32_t k = K ? K : default_k(M);
     const uint32_t lid_passes = (uint32_t)ceil_div(bits_for(num_lists - 1) ? bits_for(num_lists - 1) : 1, k);
     const uint32_t reg = reg_entries(M / 8);
-    const uint32_t cap = n <= (1ull << 26) ? 128u : reg;
+    const uint32_t cap = level0_cap(n, reg);
     const uint64_t chains0 = (uint64_t)num_lists + ceil_div(n, 1ull << kLog0);
     if (chains0 >= (uint64_t)PBIT_NIL)
         return false;

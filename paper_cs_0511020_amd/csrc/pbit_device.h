@@ -275,12 +275,48 @@ __global__ __launch_bounds__(256) void k_pack(Src src, uint32_t n, KeyT float_se
 // ---------------------------------------------------------------- unchain
 // Every level-0 chain to list order: its stored entries (up to `cap`) are
 // copied to its place, 2^kLog0 threads (the mean chain length) per chain.
-// The first kLongBlocks blocks instead take the chains longer than their slot
-// (listed by the walk) and walk their rests again from the resume node,
-// writing straight to list order; being dispatched first, that latency-bound
-// tail overlaps the copy.
-constexpr uint32_t kLongBlocks = 16;
+// A chain longer than its slot also needs the rest re-walked from its resume
+// node, one dependent load per node.  The first kLongListMax such chains are
+// listed by the walk and taken by the first kLongBlocks blocks, which are
+// dispatched first, so that latency-bound tail overlaps the copy; any further
+// ones (many when the slot is short) are walked by their own chain's first
+// thread.
+constexpr uint32_t kLongBlocks = kLongListMax / 256;
 constexpr uint32_t kUnchainThreads = 1u << kLog0;
+
+// End of a level-0 walk: where the rest of a long chain is walked from.
+// long_list holds {chain, resume node} pairs for the early blocks; resume[c]
+// is the node for the chain's own group, or kNil.
+__device__ __forceinline__ void record_long_chain(uint32_t c, uint32_t len, uint32_t cap,
+                                                  uint32_t rest_from, uint32_t* resume,
+                                                  uint32_t* long_list, Header* hdr)
+{
+    uint32_t own = kNil;
+    if (len > cap) {
+        const uint32_t k = atomicAdd(&hdr->n_long, 1u);
+        if (k < kLongListMax) {
+            long_list[2 * k] = c;
+            long_list[2 * k + 1] = rest_from;
+        } else {
+            own = rest_from;
+        }
+    }
+    resume[c] = own;
+}
+
+// Write the rest of chain c (positions cap..len-1 of the chain) from node cur.
+template <typename KeyT>
+__device__ __forceinline__ void walk_rest(const NodeRec<KeyT>* __restrict__ nodes, uint32_t cur,
+                                          uint64_t pos, uint64_t end, uint32_t n,
+                                          Pair<KeyT>* __restrict__ out)
+{
+    while (pos < end && cur < n) {
+        const NodeRec<KeyT> r = nodes[cur];
+        out[pos] = make_pair_kv<KeyT>((KeyT)r.key, cur);
+        pos++;
+        cur = r.next;
+    }
+}
 
 template <typename KeyT>
 __global__ __launch_bounds__(256) void k_unchain(const uint2* __restrict__ chain_rec,
@@ -296,21 +332,14 @@ __global__ __launch_bounds__(256) void k_unchain(const uint2* __restrict__ chain
     if (hdr->status != 0)
         return;
     if (blockIdx.x < kLongBlocks) {
-        const uint32_t n_long = hdr->n_long;
-        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_long;
-             i += kLongBlocks * blockDim.x) {
-            const uint32_t c = long_list[i];
-            if (c >= n_chains)
-                continue;
-            const uint32_t len = chain_rec[c].y;
-            uint32_t cur = resume[c];
-            uint32_t pos = offn_chain[c] + cap;
-            const uint32_t end = (uint32_t)min<uint64_t>((uint64_t)offn_chain[c] + len, (uint64_t)n);
-            while (pos < end && cur < n) {
-                const NodeRec<KeyT> r = nodes[cur];
-                out[pos] = make_pair_kv<KeyT>((KeyT)r.key, cur);
-                pos++;
-                cur = r.next;
+        const uint32_t listed = min(hdr->n_long, kLongListMax);
+        const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+        if (i < listed) {
+            const uint32_t c = long_list[2 * i];
+            if (c < n_chains) {
+                const uint64_t base = offn_chain[c];
+                walk_rest<KeyT>(nodes, long_list[2 * i + 1], base + cap,
+                                min<uint64_t>(base + chain_rec[c].y, (uint64_t)n), n, out);
             }
         }
         return;
@@ -319,10 +348,18 @@ __global__ __launch_bounds__(256) void k_unchain(const uint2* __restrict__ chain
     const uint32_t c = (uint32_t)(g / G);
     if (c >= n_chains)
         return;
-    const uint32_t len = min(chain_rec[c].y, cap);
+    const uint32_t full = chain_rec[c].y;
+    const uint32_t len = min(full, cap);
     const uint32_t base = offn_chain[c];
+    const uint32_t lead = (uint32_t)(g % G);
+    if (lead == 0 && full > cap) {
+        const uint32_t own = resume[c];
+        if (own != kNil)
+            walk_rest<KeyT>(nodes, own, (uint64_t)base + cap,
+                            min<uint64_t>((uint64_t)base + full, (uint64_t)n), n, out);
+    }
     const Entry<KeyT>* b = ent + (size_t)c * cap;
-    for (uint32_t t = (uint32_t)(g % G); t < len; t += G) {
+    for (uint32_t t = lead; t < len; t += G) {
         const uint32_t pos = base + t;
         if (pos >= n)
             break;

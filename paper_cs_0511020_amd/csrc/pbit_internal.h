@@ -24,6 +24,9 @@ constexpr uint32_t kLogUp = PBIT_LOGUP;
 // The last level is ranked inside one workgroup's LDS.
 constexpr uint32_t kBaseMax = PBIT_BASEMAX;
 constexpr int kMaxLevels = 12;
+// Chains longer than their level-0 slot that the unchain launch's first
+// blocks take (each further one is walked by its own chain's group).
+constexpr uint32_t kLongListMax = 16 * 256;
 constexpr int kMaxPasses = 96;
 
 // Lookback words: 2 flag bits + 30-bit count.
@@ -61,7 +64,7 @@ struct LevelPlan {
     size_t o_chain_rec;   // uint2 {successor chain, weight} per chain
     size_t o_ent;         // level 0: stored head entries of every chain
     size_t o_resume;      // level 0: node where the unstored rest of a chain starts
-    size_t o_long;        // level 0: ids of the chains longer than `cap` (Header::n_long)
+    size_t o_long;        // level 0: {chain, resume node} of the first long chains
     uint32_t cap;         // level 0: entries stored per chain
     size_t o_offn;        // u32 offset (in nodes) of every chain
 };

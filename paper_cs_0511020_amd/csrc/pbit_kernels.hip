@@ -90,39 +90,42 @@ __global__ __launch_bounds__(256) void k_walk0(const NodeRec<KeyT>* __restrict__
         start = (uint32_t)s;
     }
     const uint32_t lmask = (1u << kLog0) - 1u;
-    Entry<KeyT> e[C];
+    Entry<KeyT>* b = ent + (size_t)c * cap;
     uint32_t cur = start, len = 0, nx = kNil;
     bool stop = false;
+    // The slot fills C entries at a time: a block of steps keeps its entries
+    // in registers and stores them in one burst afterwards.  (A store issued
+    // between two steps would be waited for by the next step's load: loads
+    // and stores share one completion counter.)  cap is a multiple of C.
+    while (!stop && len < cap) {
+        Entry<KeyT> e[C];
+        uint32_t got = 0;
 #pragma unroll
-    for (uint32_t t = 0; t < C; t++) {
-        if (!stop) {
-            const NodeRec<KeyT> r = nodes[cur];
-            e[t].key = r.key;
-            e[t].idx = cur;
-            if constexpr (sizeof(KeyT) == 8) e[t].pad = 0;
-            len = t + 1;
-            nx = r.next;
-            if (nx == kNil || nx >= n || (nx & lmask) == 0 || nx == head)
-                stop = true;
-            else
-                cur = nx;
+        for (uint32_t t = 0; t < C; t++) {
+            if (!stop) {
+                const NodeRec<KeyT> r = nodes[cur];
+                e[t].key = r.key;
+                e[t].idx = cur;
+                if constexpr (sizeof(KeyT) == 8) e[t].pad = 0;
+                got = t + 1;
+                nx = r.next;
+                if (nx == kNil || nx >= n || (nx & lmask) == 0 || nx == head || len + got >= n)
+                    stop = true;
+                else
+                    cur = nx;
+            }
         }
+#pragma unroll
+        for (uint32_t t = 0; t < C; t++)
+            if (t < got)
+                b[len + t] = e[t];
+        len += got;
     }
-    Entry<KeyT>* b = ent + (size_t)c * cap;
-    uint32_t rest_from = stop ? kNil : (C >= cap ? cur : kNil);
+    // beyond the slot the walk only counts; unchain walks this rest again
+    const uint32_t rest_from = stop ? kNil : cur;
     while (!stop) {
-        const NodeRec<KeyT> r = nodes[cur];
-        if (len < cap) {
-            Entry<KeyT> x;
-            x.key = r.key;
-            x.idx = cur;
-            if constexpr (sizeof(KeyT) == 8) x.pad = 0;
-            b[len] = x;
-        } else if (len == cap && C < cap) {
-            rest_from = cur;
-        }
+        nx = nodes[cur].next;
         len++;
-        nx = r.next;
         if (nx == kNil || nx >= n || (nx & lmask) == 0 || nx == head || len >= n)
             stop = true;
         else
@@ -132,13 +135,7 @@ __global__ __launch_bounds__(256) void k_walk0(const NodeRec<KeyT>* __restrict__
         set_error(&hdr->status, PBIT_EMALFORMED);
         nx = kNil;
     }
-#pragma unroll
-    for (uint32_t t = 0; t < C; t++)
-        if (t < len && t < cap)
-            b[t] = e[t];
-    resume[c] = rest_from;
-    if (len > cap)
-        long_list[atomicAdd(&hdr->n_long, 1u)] = c;
+    record_long_chain(c, len, cap, rest_from, resume, long_list, hdr);
     const uint32_t succ = (nx == kNil) ? kNil : (nx == head ? 0u : 1u + (nx >> kLog0));
     chain_rec[c] = make_uint2(succ, len);
 }
