@@ -184,6 +184,24 @@ int pbit_sort_lists_profiled(const uint32_t *d_heads, const uint64_t *d_offsets,
                              int n_events, int *n_recorded);
 
 /*
+ * Nodes stored as records (the node structure of Sec. 2: the link and the
+ * data side by side) instead of separate arrays.  Node i is the record of
+ * `stride` bytes at nodes + i * stride (64-bit offsets); its next index is the
+ * uint32 at byte next_off of the record and its key the M-bit value at byte
+ * key_off.  The two fields must lie inside the record, must not overlap, and
+ * must be naturally aligned in every record (stride a multiple of 4 and of the
+ * key size, stride < 2^32).  The sort rewrites only the next field of each
+ * record, in place; every other byte is left as it was, so the data travels
+ * with its node.  Head, keys, flags, d_result, workspace (pbit_workspace_bytes
+ * with the same n, M, K), errors and asynchrony are those of
+ * pbit_sort_list_async.
+ */
+int pbit_sort_list_aos_async(uint32_t head, void *nodes, uint64_t stride, uint32_t next_off,
+                             uint32_t key_off, uint64_t n, uint32_t M, uint32_t K,
+                             uint32_t flags, uint32_t *d_result, void *ws, size_t ws_bytes,
+                             void *stream);
+
+/*
  * Doubly-linked lists (Sec. 13).  The sort relinks only next[]; this call then
  * rebuilds the backward links: prev[next[i]] = i for every node i with a
  * successor and prev[h] = PBIT_NIL for every head h in d_heads.  The paper

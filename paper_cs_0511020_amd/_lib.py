@@ -48,6 +48,10 @@ _SIGNATURES = {
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    "pbit_sort_list_aos_async": (ctypes.c_int, [
+        ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+        ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
+        ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "pbit_repair_prev_async": (ctypes.c_int, [
         ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
         ctypes.c_void_p, ctypes.c_void_p]),
@@ -135,4 +139,14 @@ def repair_prev(heads, num_lists: int, next_, prev, n: int, status=None, status_
     st_ptr = _ptr(status) + status_offset if status is not None else 0
     return int(load().pbit_repair_prev_async(
         _ptr(heads), int(num_lists), _ptr(next_), _ptr(prev), int(n), st_ptr,
+        _stream_handle(stream)))
+
+
+def sort_list_aos_async(head: int, nodes, stride: int, next_off: int, key_off: int, n: int,
+                        M: int, K: int, flags: int, result, ws, ws_bytes: int,
+                        stream=None) -> int:
+    """Raw C-ABI call for nodes stored as records of ``stride`` bytes."""
+    return int(load().pbit_sort_list_aos_async(
+        int(head) & 0xFFFFFFFF, _ptr(nodes), int(stride), int(next_off), int(key_off), int(n),
+        int(M), int(K), int(flags), _ptr(result), _ptr(ws), int(ws_bytes),
         _stream_handle(stream)))

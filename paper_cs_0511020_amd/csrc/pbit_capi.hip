@@ -14,6 +14,9 @@ namespace pbit {
 hipError_t enqueue_sort(const Plan& P, uint32_t head, const uint32_t* next_in, uint32_t* next_out,
                         const void* keys, uint32_t* d_result, char* ws, hipStream_t s, Prof* prof);
 hipError_t enqueue_empty(uint32_t* d_result, hipStream_t s);
+hipError_t enqueue_sort_aos(const Plan& P, uint32_t head, char* base, uint64_t stride,
+                            uint32_t next_off, uint32_t key_off, uint32_t* d_result, char* ws,
+                            hipStream_t s, Prof* prof);
 hipError_t enqueue_sort_lists(const Plan& P, const uint32_t* heads, const uint64_t* offsets,
                               const uint32_t* next_in, uint32_t* next_out, const void* keys,
                               const uint64_t* next_in_ptrs, const uint64_t* next_out_ptrs,
@@ -288,6 +291,43 @@ extern "C" int pbit_sort_list_profiled(uint32_t head, const uint32_t* next_in,
                                   ws_bytes, stream, &prof);
     *n_recorded = prof.count;
     return st;
+}
+
+extern "C" int pbit_sort_list_aos_async(uint32_t head, void* nodes, uint64_t stride,
+                                        uint32_t next_off, uint32_t key_off, uint64_t n,
+                                        uint32_t M, uint32_t K, uint32_t flags,
+                                        uint32_t* d_result, void* ws, size_t ws_bytes,
+                                        void* stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    if (!d_result || ((uintptr_t)d_result & 3u))
+        return PBIT_EINVAL;
+    Plan P;
+    if (!make_plan(n, M, K, flags, &P))
+        return PBIT_EINVAL;
+    if (n == 0) {
+        if (head != PBIT_NIL)
+            return PBIT_EINVAL;
+        return enqueue_empty(d_result, s) == hipSuccess ? PBIT_OK : PBIT_EHIP;
+    }
+    const uint64_t kb = P.key_bytes;
+    const uintptr_t base = (uintptr_t)nodes;
+    if (head >= n || !nodes || !ws)
+        return PBIT_EINVAL;
+    // both fields inside the record, apart, and naturally aligned in every record
+    if (stride < 4 || stride >= (1ull << 32) || (stride & 3u) || (stride % kb) != 0)
+        return PBIT_EINVAL;
+    if ((uint64_t)next_off + 4 > stride || (uint64_t)key_off + kb > stride)
+        return PBIT_EINVAL;
+    if (!((uint64_t)next_off + 4 <= key_off || (uint64_t)key_off + kb <= next_off))
+        return PBIT_EINVAL;
+    if (((base + next_off) & 3u) || ((base + key_off) & (kb - 1)) || ((uintptr_t)ws & 255u))
+        return PBIT_EINVAL;
+    if (ws_bytes < P.total)
+        return PBIT_ENOMEM;
+    hipError_t e = enqueue_sort_aos(P, head, (char*)nodes, stride, next_off, key_off, d_result,
+                                    (char*)ws, s, nullptr);
+    return e == hipSuccess ? PBIT_OK : PBIT_EHIP;
 }
 
 extern "C" int pbit_repair_prev_async(const uint32_t* d_heads, uint32_t num_lists,

@@ -144,6 +144,24 @@ template <typename KeyT> struct DirectSrc {
     }
 };
 
+// ... or records of `stride` bytes (the paper's node structure, Sec. 2: the
+// link and the data side by side): node i's next index is the uint32 at byte
+// next_off of record i, its key the KeyT at byte key_off.
+template <typename KeyT> struct AosSrc {
+    const char* base;
+    uint64_t stride;
+    uint32_t next_off;
+    uint32_t key_off;
+    __device__ __forceinline__ void load(size_t i, uint32_t n, uint32_t& nx, KeyT& k,
+                                         bool& bad) const
+    {
+        const char* r = base + (uint64_t)i * stride;
+        nx = *(const uint32_t*)(r + next_off);
+        k = *(const KeyT*)(r + key_off);
+        bad |= (nx != kNil) && (nx >= n);
+    }
+};
+
 // Node -> list of a many-list sort: lists own contiguous node ranges
 // [offsets[l], offsets[l+1]); table[b] is the list holding node b << log_block.
 struct LidMap {

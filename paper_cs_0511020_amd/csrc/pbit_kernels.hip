@@ -298,8 +298,10 @@ __global__ __launch_bounds__(256) void k_down(const uint2* __restrict__ recs, ui
 
 // ---------------------------------------------------------------- relink
 // next[order[j]] = order[j+1]; the last node gets NIL; result = {head, status}.
+// next_out: node i's new link goes to the uint32 at out_base + i * out_stride
+// (a plain array: stride 4; records: the record stride).
 __global__ __launch_bounds__(256) void k_relink(OrderSrc src, uint32_t n,
-                                                uint32_t* __restrict__ next_out,
+                                                char* __restrict__ out_base, uint64_t out_stride,
                                                 uint32_t* __restrict__ result, const Header* hdr)
 {
     const int32_t st = hdr->status;
@@ -316,7 +318,7 @@ __global__ __launch_bounds__(256) void k_relink(OrderSrc src, uint32_t n,
         const uint32_t node = order_at(src, kind, j);
         const uint32_t succ = (j + 1 < n) ? order_at(src, kind, j + 1) : kNil;
         if (node < n)
-            next_out[node] = succ;
+            *(uint32_t*)(out_base + (uint64_t)node * out_stride) = succ;
         if (j == 0) {
             result[0] = node;
             result[1] = 0;
@@ -343,16 +345,19 @@ static hipError_t launch_walk0(const Plan& P, uint32_t head, char* ws, hipStream
     return hipGetLastError();
 }
 
-// Everything after the plan: the whole path queued on one stream.
+// Everything after pack: ranking, list order, passes, relink.
+static hipError_t enqueue_after_pack(const Plan& P, uint32_t head, char* out_base,
+                                     uint64_t out_stride, uint32_t* d_result, char* ws,
+                                     hipStream_t s, Prof* prof);
+
+// The whole path queued on one stream.
 hipError_t enqueue_sort(const Plan& P, uint32_t head, const uint32_t* next_in, uint32_t* next_out,
                         const void* keys, uint32_t* d_result, char* ws, hipStream_t s, Prof* prof)
 {
     hipError_t e;
     mark(prof, s, kStageZero);
-    {
-        if ((e = launch_zero(P, ws, s)) != hipSuccess)
-            return e;
-    }
+    if ((e = launch_zero(P, ws, s)) != hipSuccess)
+        return e;
     mark(prof, s, kStagePack);
     switch (P.key_bytes) {
     case 1: e = launch_pack<uint8_t>(P, next_in, keys, ws, s); break;
@@ -362,6 +367,35 @@ hipError_t enqueue_sort(const Plan& P, uint32_t head, const uint32_t* next_in, u
     }
     if (e != hipSuccess)
         return e;
+    return enqueue_after_pack(P, head, (char*)next_out, 4, d_result, ws, s, prof);
+}
+
+// The same for nodes stored as records; the links are rewritten in place.
+hipError_t enqueue_sort_aos(const Plan& P, uint32_t head, char* base, uint64_t stride,
+                            uint32_t next_off, uint32_t key_off, uint32_t* d_result, char* ws,
+                            hipStream_t s, Prof* prof)
+{
+    hipError_t e;
+    mark(prof, s, kStageZero);
+    if ((e = launch_zero(P, ws, s)) != hipSuccess)
+        return e;
+    mark(prof, s, kStagePack);
+    switch (P.key_bytes) {
+    case 1: e = launch_pack_src<uint8_t>(P, AosSrc<uint8_t>{base, stride, next_off, key_off}, ws, s); break;
+    case 2: e = launch_pack_src<uint16_t>(P, AosSrc<uint16_t>{base, stride, next_off, key_off}, ws, s); break;
+    case 4: e = launch_pack_src<uint32_t>(P, AosSrc<uint32_t>{base, stride, next_off, key_off}, ws, s); break;
+    default: e = launch_pack_src<uint64_t>(P, AosSrc<uint64_t>{base, stride, next_off, key_off}, ws, s); break;
+    }
+    if (e != hipSuccess)
+        return e;
+    return enqueue_after_pack(P, head, base + next_off, stride, d_result, ws, s, prof);
+}
+
+static hipError_t enqueue_after_pack(const Plan& P, uint32_t head, char* out_base,
+                                     uint64_t out_stride, uint32_t* d_result, char* ws,
+                                     hipStream_t s, Prof* prof)
+{
+    hipError_t e;
     mark(prof, s, kStageWalk0);
     switch (P.key_bytes) {
     case 1: e = launch_walk0<uint8_t>(P, head, ws, s); break;
@@ -422,8 +456,8 @@ hipError_t enqueue_sort(const Plan& P, uint32_t head, const uint32_t* next_in, u
         uint32_t blocks = (uint32_t)((P.n + 255) / 256);
         mark(prof, s, kStageRelink);
         const OrderSrc src = P.key_bytes == 8 ? order_src<uint64_t>(P, ws) : order_src<uint32_t>(P, ws);
-        hipLaunchKernelGGL(k_relink, dim3(blocks), dim3(256), 0, s, src, (uint32_t)P.n, next_out,
-                           d_result, (const Header*)hdr);
+        hipLaunchKernelGGL(k_relink, dim3(blocks), dim3(256), 0, s, src, (uint32_t)P.n, out_base,
+                           out_stride, d_result, (const Header*)hdr);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }

@@ -105,6 +105,35 @@ class ListSorter:
         return h & 0xFFFFFFFF
 
 
+    def sort_aos_async(self, head: int, nodes: torch.Tensor, n: int, stride: int, next_off: int,
+                       key_off: int, M: int, K: int = 0, descending: bool = False,
+                       signed: bool = False, floating: bool = False, result=None,
+                       stream=None) -> torch.Tensor:
+        """Sort nodes stored as records of ``stride`` bytes in ``nodes`` (any
+        dtype; byte offsets): the next index is the uint32 at ``next_off``, the
+        key the M-bit value at ``key_off``.  Links are rewritten in place."""
+        if result is None:
+            result = self.result
+        if int(nodes.numel()) * nodes.element_size() < n * stride:
+            raise ValueError("nodes holds fewer than n records")
+        ws = self.workspace(n, M, K)
+        flags = ((_lib.DESCENDING if descending else 0) | (_lib.SIGNED if signed else 0)
+                 | (_lib.FLOAT if floating else 0))
+        st = _lib.sort_list_aos_async(head, nodes, stride, next_off, key_off, n, M, K, flags,
+                                      result, ws, self._ws_bytes, stream)
+        if st != _lib.OK:
+            raise PbitError(st)
+        return result
+
+    def sort_aos(self, head: int, nodes: torch.Tensor, n: int, stride: int, next_off: int,
+                 key_off: int, M: int, K: int = 0, **kw) -> int:
+        res = self.sort_aos_async(head, nodes, n, stride, next_off, key_off, M, K, **kw)
+        h, st = (int(x) for x in res.cpu().tolist())
+        if st != 0:
+            raise PbitError(st)
+        return h & 0xFFFFFFFF
+
+
 class ListsSorter:
     """Sort many lists in one launch sequence (lists in contiguous node slabs).
 

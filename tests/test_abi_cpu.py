@@ -91,6 +91,27 @@ def test_host_argument_checks(lib):
     assert lib.pbit_sort_list(_lib.NIL, 0, 0, 0, 32, 4) == _lib.NIL
 
 
+def test_aos_host_checks(lib):
+    E = _lib.EINVAL
+    f = lib.pbit_sort_list_aos_async
+
+    def call(head=0, nodes=0x10000, stride=8, next_off=0, key_off=4, n=8, M=32, K=8, flags=0,
+             res=0x2000, ws=0x100000, wsb=1 << 40):
+        return f(head, nodes, stride, next_off, key_off, n, M, K, flags, res, ws, wsb, None)
+    assert call(stride=2) == E                   # too short for a link
+    assert call(stride=10) == E                  # not a multiple of 4
+    assert call(key_off=2) == E                  # key overlaps the link
+    assert call(next_off=6, stride=12) == E      # misaligned link
+    assert call(key_off=6, M=32, stride=12) == E  # misaligned key
+    assert call(key_off=8) == E                  # key past the record
+    assert call(M=64, key_off=4, stride=16) == E  # 8-byte key not 8-aligned
+    assert call(stride=1 << 32) == E
+    assert call(nodes=0) == E
+    assert call(head=8) == E
+    assert call(K=3) == E
+    assert call(wsb=16) == _lib.ENOMEM
+
+
 def test_repair_prev_host_checks(lib):
     E = _lib.EINVAL
     f = lib.pbit_repair_prev_async
