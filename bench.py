@@ -474,23 +474,31 @@ def run_served(args, torch, np, inputs):
     reset(np.zeros(count))
     sat = SortServer(GpuExecutor(streams=2), slots=64, budget_bytes=budget).run(reqs)
     X = sat.throughput_mnodes_s * 1e6
-    rng = inputs.rng_for(5002)
-    lam = 0.7 * X / mean_len
-    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=count))
-    reset(arrivals)
-    opened = SortServer(GpuExecutor(streams=2), slots=64, budget_bytes=budget).run(reqs)
     ok = all(r.status == 0 for r in reqs)
-    reset(arrivals)
-    fifo = SortServer(PlainExecutor(), slots=1, budget_bytes=budget).run(reqs)
+    loads = {}
+    for frac in ((0.5, 0.7, 0.9) if full else (0.7,)):
+        rng = inputs.rng_for(5002)
+        lam = frac * X / mean_len
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, size=count))
+        reset(arrivals)
+        opened = SortServer(GpuExecutor(streams=2), slots=64, budget_bytes=budget).run(reqs)
+        ok = ok and all(r.status == 0 for r in reqs)
+        reset(arrivals)
+        fifo = SortServer(PlainExecutor(), slots=1, budget_bytes=budget).run(reqs)
+        ok = ok and all(r.status == 0 for r in reqs)
+        loads[frac] = (summary(opened), summary(fifo))
+    opened_s, fifo_s = loads[0.7]
     out = {
         "workload": "%d requests, lengths log-uniform in [2^10, 2^%d], key widths uniform over "
-                    "{8,16,32,64}, uniform keys, device-resident, Poisson arrivals at 0.7 of the "
-                    "saturated rate" % (count, hi),
+                    "{8,16,32,64}, uniform keys, device-resident, Poisson arrivals at %s of the "
+                    "saturated rate" % (count, hi, "0.5/0.7/0.9" if full else "0.7"),
         "nodes": int(sum(r.n for r in reqs)),
         "saturated": summary(sat),
         "offered_mnodes_s": round(0.7 * X / 1e6, 1),
-        "batched_open_loop": summary(opened),
-        "fifo_plain_open_loop": summary(fifo),
+        "batched_open_loop": opened_s,
+        "fifo_plain_open_loop": fifo_s,
+        "by_load": {"%.1f" % f: {"offered_mnodes_s": round(f * X / 1e6, 1), "batched": b,
+                                 "fifo_plain": p} for f, (b, p) in loads.items()},
         "all_ok": ok,
     }
     del reqs

@@ -101,8 +101,7 @@ static bool plan_common(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, uint
     off = align_up(off + n * pair_bytes(P->key_bytes));
     P->o_idxA = off;
     off = align_up(off + n * 4);
-    P->o_idxB = off;
-    off = align_up(off + n * 4);
+    P->o_idxB = P->o_idxA;  // node indices are written once, by the last pass
     LevelPlan& L = P->lv[0];
     L.log_l = kLog0;
     L.m = n;

@@ -425,25 +425,37 @@ __global__ __launch_bounds__(256) void k_schedule(const uint32_t* __restrict__ h
         __syncthreads();
     }
     if (tid == 0) {
-        // The list order starts as pairs A.  Key passes go pairs to pairs, the
-        // last one that runs to index buffer A; list-id passes go index buffer
-        // to index buffer (or from pairs A when every key pass was skipped).
-        int last_key = -1;
-        for (uint32_t p = 0; p < key_passes; p++)
-            if (!s_skip[p])
+        // The list order starts as (key, node) pairs A.  Key passes go pairs to
+        // pairs; the last one that runs writes (list id, node) pairs when
+        // list-id passes follow, else node indices.  List-id passes go list-id
+        // pairs to list-id pairs, the last one that runs to node indices.
+        // (When every key pass was skipped the first list-id pass reads pairs A
+        // and looks the list ids up itself.)
+        int last_key = -1, last_lid = -1;
+        for (uint32_t p = 0; p < passes; p++) {
+            if (s_skip[p])
+                continue;
+            if (p < key_passes)
                 last_key = (int)p;
+            else
+                last_lid = (int)p;
+        }
         uint32_t cur = kBufPairsA;
         for (uint32_t p = 0; p < passes; p++) {
             PassSched ps;
             ps.skip = s_skip[p];
             ps.in_kind = cur;
             ps.pad = 0;
-            if (p < key_passes)
-                ps.out_kind = (int)p == last_key ? (uint32_t)kBufIdxA
-                                                 : (cur == kBufPairsA ? (uint32_t)kBufPairsB
-                                                                      : (uint32_t)kBufPairsA);
-            else
-                ps.out_kind = cur == kBufIdxA ? (uint32_t)kBufIdxB : (uint32_t)kBufIdxA;
+            // the other half of the ping-pong memory, in either pair format
+            const bool in_a = cur == kBufPairsA || cur == kBufLidA;
+            if (p < key_passes) {
+                if ((int)p == last_key)
+                    ps.out_kind = last_lid >= 0 ? (in_a ? kBufLidB : kBufLidA) : kBufIdxA;
+                else
+                    ps.out_kind = in_a ? kBufPairsB : kBufPairsA;
+            } else {
+                ps.out_kind = (int)p == last_lid ? kBufIdxA : (in_a ? kBufLidB : kBufLidA);
+            }
             if (!ps.skip)
                 cur = ps.out_kind;
             hdr->sched[p] = ps;
@@ -506,14 +518,17 @@ __global__ __launch_bounds__(BLOCK, 4) void k_digit_pass(uint32_t pass, uint32_t
     const PassSched ps = hdr->sched[pass];
     if (ps.skip)
         return;
-    // key passes read pairs; list-id passes read indices (or pairs A's idx
-    // field when every key pass was skipped); only key passes before the last
-    // one write pairs
-    const bool in_pairs = ps.in_kind < kBufIdxA;
+    // key passes read (key, node) pairs and write pairs, or from the last one
+    // (list id, node) pairs or node indices; list-id passes read (list id,
+    // node) pairs (or pairs A, looking list ids up, when every key pass was
+    // skipped) and write (list id, node) pairs or, from the last, node indices
+    const bool in_lid = ps.in_kind >= kBufLidA;
     const bool out_pairs = ps.out_kind < kBufIdxA;
+    const bool out_lid = ps.out_kind >= kBufLidA;
     const Pair<KeyT>* pin = ps.in_kind == kBufPairsB ? pairsB : pairsA;
-    const uint32_t* iin = ps.in_kind == kBufIdxB ? idxB : idxA;
+    const uint2* lin = (const uint2*)(ps.in_kind == kBufLidB ? (const void*)pairsB : (const void*)pairsA);
     Pair<KeyT>* pout = ps.out_kind == kBufPairsB ? pairsB : pairsA;
+    uint2* lout = (uint2*)(ps.out_kind == kBufLidB ? (void*)pairsB : (void*)pairsA);
     uint32_t* iout = ps.out_kind == kBufIdxB ? idxB : idxA;
 
     const uint32_t tid = threadIdx.x;
@@ -536,8 +551,14 @@ __global__ __launch_bounds__(BLOCK, 4) void k_digit_pass(uint32_t pass, uint32_t
         const uint64_t e = wbase + (uint64_t)i * 64 + lane;
         if (e < n) {
             if constexpr (LID) {
-                idx[i] = in_pairs ? pin[e].idx : iin[e];
-                key[i] = list_of(lm, idx[i]);
+                if (in_lid) {
+                    const uint2 v = lin[e];
+                    key[i] = v.x;
+                    idx[i] = v.y;
+                } else {
+                    idx[i] = pin[e].idx;
+                    key[i] = list_of(lm, idx[i]);
+                }
             } else {
                 const Pair<KeyT> v = pin[e];
                 key[i] = (SKey)pair_key<KeyT>(v);
@@ -640,7 +661,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_digit_pass(uint32_t pass, uint32_t
                     for (uint64_t q = b0; q < b1; q++) {
                         uint32_t x;
                         if constexpr (LID)
-                            x = list_of(lm, in_pairs ? pin[q].idx : iin[q]);
+                            x = in_lid ? lin[q].x : list_of(lm, pin[q].idx);
                         else
                             x = (uint32_t)(pair_key<KeyT>(pin[q]) >> shift);
                         if constexpr (LID)
@@ -686,6 +707,8 @@ __global__ __launch_bounds__(BLOCK, 4) void k_digit_pass(uint32_t pass, uint32_t
             if (g < n) {
                 if (!LID && out_pairs)
                     pout[g] = make_pair_kv<KeyT>((KeyT)kv.key, kv.idx);
+                else if (out_lid)  // the last key pass looks each node's list up once
+                    lout[g] = make_uint2(LID ? (uint32_t)kv.key : list_of(lm, kv.idx), kv.idx);
                 else
                     iout[g] = kv.idx;
             }

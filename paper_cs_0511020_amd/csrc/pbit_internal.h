@@ -34,9 +34,12 @@ constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagPrefix = 2u << 30;
 constexpr uint32_t kCountMask = (1u << 30) - 1u;
 
-// List-order buffers: (key, node) pairs while key passes remain, node
-// indices alone after the last key pass.
-enum BufKind : uint32_t { kBufPairsA = 0, kBufPairsB = 1, kBufIdxA = 2, kBufIdxB = 3 };
+// List-order buffers: (key, node) pairs while key passes remain; (list id,
+// node) pairs (in the same memory, 8 bytes each) while list-id passes remain;
+// node indices alone after the last pass.
+enum BufKind : uint32_t {
+    kBufPairsA = 0, kBufPairsB = 1, kBufIdxA = 2, kBufIdxB = 3, kBufLidA = 4, kBufLidB = 5
+};
 
 struct PassSched {
     uint32_t skip;      // every element has the same digit: the pass is the identity
