@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--served", default="small", choices=["none", "small", "full"],
                     help="served section: 300 requests up to 2^20 nodes (small) or 2000 up "
                          "to 2^24 (full)")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the graph-replay timing of the single-list sort")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the float-key sort and the backward-link repair timings")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -160,6 +162,32 @@ def run_plain(args, lib, torch, np, inputs, bytemodel, EventPool):
     exp_order = order[np.argsort(keys[order], kind="stable")]
     ok = (h0 == int(exp_order[0])) and bool(np.array_equal(got[exp_order[:-1]], exp_order[1:]))
 
+    # the same sort captured once in a HIP graph and replayed (no per-kernel
+    # launch work on the host); reported beside the eager rate
+    graph_ms = None
+    if not args.no_graph:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            st = lib.pbit_sort_list_async(head, next_in.data_ptr(), next_out.data_ptr(),
+                                          keys_d.data_ptr(), n, M, K, 0, result.data_ptr(),
+                                          ws.data_ptr(), ws_bytes,
+                                          int(torch.cuda.current_stream().cuda_stream))
+            if st != 0:
+                raise RuntimeError("capture failed: " + _lib.status_string(st))
+        torch.cuda.current_stream().wait_stream(side)
+        for _ in range(2):
+            g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.replay()
+        torch.cuda.synchronize()
+        graph_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        ok = ok and bool(np.array_equal(next_out.cpu().numpy().view(np.uint32), got))
+        del g
+
     w = M // 8
     executed = launches.get("digit_pass", passes)
     path_bpn = bytemodel.path_bytes_per_node(w, executed)
@@ -191,6 +219,7 @@ def run_plain(args, lib, torch, np, inputs, bytemodel, EventPool):
         "value": n / (wall_ms * 1e-3) / 1e6, "wall_ms": wall_ms, "p50": p50, "p99": p99,
         "roofline": roofline, "stage_ms": stage_ms, "launches": launches, "correct": ok,
         "path_bpn": path_bpn, "path_frac": path_frac, "Keff": Keff, "src_hash": src_hash,
+        "graph_ms": graph_ms,
     }
 
 
@@ -586,6 +615,8 @@ def main():
         "roofline": r["roofline"],
         "cpu_baseline": cpu,
         "latency_ms": {"p50": round(r["p50"], 4), "p99": round(r["p99"], 4)},
+        "graph_replay_ms_per_step": (round(r["graph_ms"], 4) if r["graph_ms"] is not None
+                                     else None),
         "path_roofline": {"bytes_per_node": r["path_bpn"], "frac_at_p50": round(r["path_frac"], 4)},
         "stages_ms": {k: round(v, 4) for k, v in sorted(r["stage_ms"].items(), key=lambda x: -x[1])},
         "stage_launches": r["launches"],
