@@ -24,7 +24,7 @@ hipError_t enqueue_sort_lists(const Plan& P, const uint32_t* heads, const uint64
                               char* ws, hipStream_t s, Prof* prof);
 hipError_t enqueue_repair_prev(const uint32_t* heads, uint32_t num_lists, const uint32_t* next,
                                uint32_t* prev, uint32_t n, int32_t* status, hipStream_t s);
-uint32_t pass_tile(uint32_t key_bytes);
+uint32_t pass_tile(uint32_t key_bytes, uint32_t rb);
 
 static size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
@@ -81,7 +81,7 @@ static bool plan_common(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, uint
         return false;
     P->flags = flags;
     P->key_bytes = M / 8;
-    P->tile = pass_tile(P->key_bytes);
+    P->tile = pass_tile(P->key_bytes, P->RB);
     P->tiles = (uint32_t)ceil_div(n ? n : 1, P->tile);
     off = 0;
     P->o_header = off;

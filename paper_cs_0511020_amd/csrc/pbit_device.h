@@ -74,6 +74,13 @@ template <typename KeyT> struct SegLen { static constexpr uint32_t value = sizeo
 // Digit-pass tile: kPassBlock threads x PassItems items.
 constexpr int kPassBlock = 1024;
 template <typename KeyT> struct PassItems { static constexpr int value = sizeof(KeyT) == 8 ? 8 : 16; };
+// Threads per digit-pass block for a pattern of RB bits.  Narrow patterns
+// need little LDS besides the tile, so a half-size tile lets two blocks share
+// a CU and overlap one's ranking with the other's memory traffic.
+#ifndef PBIT_NARROW_BLOCK
+#define PBIT_NARROW_BLOCK 512
+#endif
+template <int RB> struct PassBlock { static constexpr int value = RB <= 4 ? PBIT_NARROW_BLOCK : kPassBlock; };
 // Consecutive tiles given to one XCD in a row.  Work-groups go to the 8 XCDs
 // round-robin by block index, so block b takes tile
 //   (q / C) * 8C + (b % 8) * C + q % C,  q = b / 8, C = kPassChunk:

@@ -33,7 +33,11 @@
 
 namespace pbit {
 
-uint32_t pass_tile(uint32_t key_bytes) { return kPassBlock * (key_bytes == 8 ? 8 : 16); }
+uint32_t pass_tile(uint32_t key_bytes, uint32_t rb)
+{
+    const uint32_t block = rb <= 4 ? (uint32_t)PassBlock<4>::value : (uint32_t)PassBlock<8>::value;
+    return block * (key_bytes == 8 ? 8u : 16u);
+}
 
 // A single list passes the in-degree check if exactly one next[] is NIL and
 // the hash sums over next[] match all nodes but the head.

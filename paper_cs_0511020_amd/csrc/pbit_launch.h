@@ -67,7 +67,7 @@ template <typename KeyT, int RB, typename LW>
 static hipError_t launch_passes_rb(const Plan& P, char* ws, hipStream_t s, Prof* prof,
                                    const LidMap& lm)
 {
-    constexpr int BLOCK = kPassBlock;
+    constexpr int BLOCK = PassBlock<RB>::value;
     constexpr int ITEMS = PassItems<KeyT>::value;
     constexpr uint32_t RADIX = 1u << RB;
     mark(prof, s, kStageSchedule);
