@@ -473,15 +473,16 @@ __global__ __launch_bounds__(256) void k_schedule(const uint32_t* __restrict__ h
 
 // ---------------------------------------------------------------- digit pass
 // One stable split on the pattern at bit `shift`.  A tile of BLOCK * ITEMS
-// consecutive list positions (tile = block index) is loaded wave-striped,
-// ranked per wave (K ballots give each item the mask of lanes with the same
-// digit; the first lane of each group adds the group size to a wave-private
-// LDS counter with one in-order LDS atomic, and peers take the returned base
-// from it), scanned across waves, chained across tiles by decoupled look-back
-// (Merrill & Garland), staged in LDS grouped by digit and written out in
-// runs.  The look-back spin is bounded: a tile that waits too long on a
-// predecessor counts that predecessor's digit in its input itself, so no
-// tile ever waits on a tile that has not been scheduled.
+// consecutive list positions (block -> tile in XCD chunks, see kPassChunk) is
+// loaded wave-striped and ranked per wave: an item's peers (the lanes whose
+// item has the same digit) come from a per-wave LDS lane mask per digit; the
+// first lane of each peer group adds the group size to a wave-private LDS
+// counter (items in program order) and its peers take the returned base from
+// it.  Counts are scanned across waves, tiles are chained by decoupled
+// look-back (Merrill & Garland), and the tile is staged in LDS grouped by
+// digit and written out in runs.  The look-back spin is bounded: a tile that
+// waits too long on a predecessor counts that predecessor's digit in its
+// input itself, so no tile ever waits on a tile that has not been scheduled.
 //
 // LW is the look-back word: 2 flag bits over a 30-bit count (uint32_t, for
 // n < 2^30) or 2 flag bits over a 32-bit count (uint64_t).  With LID the
@@ -518,7 +519,11 @@ __global__ __launch_bounds__(BLOCK, 4) void k_digit_pass(uint32_t pass, uint32_t
     __shared__ uint32_t s_count[RADIX];
     __shared__ uint32_t s_start[RADIX];
     __shared__ uint32_t s_delta[RADIX];
-    __shared__ KV<SKey> s_kv[TILE];
+    __shared__ __attribute__((aligned(16))) KV<SKey> s_kv[TILE];
+    // during ranking the start of s_kv holds one 64-bit lane mask per digit
+    // per wave (it is staged into only afterwards)
+    static_assert((size_t)WAVES * RADIX * 8 <= sizeof(KV<SKey>) * TILE, "peer masks fit in s_kv");
+    unsigned long long* s_mask = (unsigned long long*)s_kv;
 
     if (hdr->status != 0)
         return;
@@ -540,8 +545,10 @@ __global__ __launch_bounds__(BLOCK, 4) void k_digit_pass(uint32_t pass, uint32_t
 
     const uint32_t tid = threadIdx.x;
     const uint32_t wave = tid / 64, lane = tid % 64;
-    for (uint32_t i = tid; i < WAVES * RADIX; i += BLOCK)
+    for (uint32_t i = tid; i < WAVES * RADIX; i += BLOCK) {
         (&s_wave[0][0])[i] = 0;
+        s_mask[i] = 0ull;
+    }
     __syncthreads();
     const uint32_t q = blockIdx.x / 8u;
     const uint32_t tile = (q / kPassChunk) * (8u * kPassChunk) + (blockIdx.x % 8u) * kPassChunk +
@@ -581,16 +588,26 @@ __global__ __launch_bounds__(BLOCK, 4) void k_digit_pass(uint32_t pass, uint32_t
     // dig[i] bits: 0..8 digit (RADIX = invalid), 16..21 rank in the wave's
     // group, 24..29 the group's first lane (which holds the LDS base)
     const uint64_t lt = lanemask_lt();
+    unsigned long long* w_mask = s_mask + (size_t)wave * RADIX;
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
         const bool valid = dig[i] < RADIX;
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < RB; b++) {
-            const bool bit = (dig[i] >> b) & 1u;
-            const uint64_t bb = __ballot(bit);
-            peers &= bit ? bb : ~bb;
-        }
+        // peers = the lanes of this wave whose item i has the same digit: each
+        // lane ORs its bit into its digit's mask, reads the mask back, and
+        // clears it.  OR is order-independent, so the mask is exact however
+        // the LDS serialises lanes that hit the same word; a wave's LDS
+        // operations complete in issue order.
+        if (valid)
+            __hip_atomic_fetch_or(&w_mask[dig[i]], 1ull << lane, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_WAVEFRONT);
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t peers = valid ? (uint64_t)__hip_atomic_load(&w_mask[dig[i]], __ATOMIC_RELAXED,
+                                                                   __HIP_MEMORY_SCOPE_WAVEFRONT)
+                                     : 0ull;
+        __builtin_amdgcn_wave_barrier();
+        if (valid)
+            __hip_atomic_store(&w_mask[dig[i]], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        __builtin_amdgcn_wave_barrier();
         const uint32_t below = (uint32_t)__popcll(peers & lt);
         const uint32_t first = valid ? (uint32_t)(__ffsll((unsigned long long)peers) - 1) : lane;
         uint32_t base = 0;
