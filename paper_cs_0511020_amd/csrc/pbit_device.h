@@ -407,6 +407,7 @@ __global__ __launch_bounds__(256) void k_schedule(const uint32_t* __restrict__ h
     constexpr uint32_t RADIX = 1u << RB;
     __shared__ uint32_t s_v[RADIX];
     __shared__ uint32_t s_skip[kMaxPasses];
+    __shared__ uint32_t s_skew[kMaxPasses];
     const uint32_t tid = threadIdx.x;
     for (uint32_t p = 0; p < passes; p++) {
         uint32_t v = 0;
@@ -417,6 +418,10 @@ __global__ __launch_bounds__(256) void k_schedule(const uint32_t* __restrict__ h
         __syncthreads();
         const int full = (tid < RADIX) && (v == n);
         const int any_full = __syncthreads_or(full);
+        // a digit holding over 1/16 of the elements makes many lanes of a
+        // wave share one LDS mask word; such passes rank by ballots instead
+        const int heavy = (tid < RADIX) && ((uint64_t)v * 16u > (uint64_t)n);
+        const int any_heavy = __syncthreads_or(heavy);
         if (tid == 0) {
             uint32_t sum = 0;
             for (uint32_t d = 0; d < RADIX; d++) {
@@ -425,6 +430,7 @@ __global__ __launch_bounds__(256) void k_schedule(const uint32_t* __restrict__ h
                 sum += x;
             }
             s_skip[p] = any_full ? 1u : 0u;
+            s_skew[p] = any_heavy ? 1u : 0u;
         }
         __syncthreads();
         if (tid < RADIX)
@@ -452,7 +458,7 @@ __global__ __launch_bounds__(256) void k_schedule(const uint32_t* __restrict__ h
             PassSched ps;
             ps.skip = s_skip[p];
             ps.in_kind = cur;
-            ps.pad = 0;
+            ps.ballot = s_skew[p];
             // the other half of the ping-pong memory, in either pair format
             const bool in_a = cur == kBufPairsA || cur == kBufLidA;
             if (p < key_passes) {
@@ -475,7 +481,9 @@ __global__ __launch_bounds__(256) void k_schedule(const uint32_t* __restrict__ h
 // One stable split on the pattern at bit `shift`.  A tile of BLOCK * ITEMS
 // consecutive list positions (block -> tile in XCD chunks, see kPassChunk) is
 // loaded wave-striped and ranked per wave: an item's peers (the lanes whose
-// item has the same digit) come from a per-wave LDS lane mask per digit; the
+// item has the same digit) come from a per-wave LDS lane mask per digit (or,
+// when one digit is frequent enough to make lanes queue on one mask word,
+// from K ballots, as the schedule decides per pass); the
 // first lane of each peer group adds the group size to a wave-private LDS
 // counter (items in program order) and its peers take the returned base from
 // it.  Counts are scanned across waves, tiles are chained by decoupled
@@ -589,25 +597,39 @@ __global__ __launch_bounds__(BLOCK, 4) void k_digit_pass(uint32_t pass, uint32_t
     // group, 24..29 the group's first lane (which holds the LDS base)
     const uint64_t lt = lanemask_lt();
     unsigned long long* w_mask = s_mask + (size_t)wave * RADIX;
+    const bool by_ballot = ps.ballot != 0;
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
         const bool valid = dig[i] < RADIX;
-        // peers = the lanes of this wave whose item i has the same digit: each
-        // lane ORs its bit into its digit's mask, reads the mask back, and
-        // clears it.  OR is order-independent, so the mask is exact however
-        // the LDS serialises lanes that hit the same word; a wave's LDS
-        // operations complete in issue order.
-        if (valid)
-            __hip_atomic_fetch_or(&w_mask[dig[i]], 1ull << lane, __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_WAVEFRONT);
-        __builtin_amdgcn_wave_barrier();
-        const uint64_t peers = valid ? (uint64_t)__hip_atomic_load(&w_mask[dig[i]], __ATOMIC_RELAXED,
-                                                                   __HIP_MEMORY_SCOPE_WAVEFRONT)
-                                     : 0ull;
-        __builtin_amdgcn_wave_barrier();
-        if (valid)
-            __hip_atomic_store(&w_mask[dig[i]], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        __builtin_amdgcn_wave_barrier();
+        // peers = the lanes of this wave whose item i has the same digit
+        uint64_t peers;
+        if (by_ballot) {
+            // K ballots: a cost independent of the digit mix
+            peers = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < RB; b++) {
+                const bool bit = (dig[i] >> b) & 1u;
+                const uint64_t bb = __ballot(bit);
+                peers &= bit ? bb : ~bb;
+            }
+        } else {
+            // each lane ORs its bit into its digit's mask, reads the mask
+            // back, and clears it.  OR is order-independent, so the mask is
+            // exact however the LDS serialises lanes that hit the same word;
+            // a wave's LDS operations complete in issue order.
+            if (valid)
+                __hip_atomic_fetch_or(&w_mask[dig[i]], 1ull << lane, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_WAVEFRONT);
+            __builtin_amdgcn_wave_barrier();
+            peers = valid ? (uint64_t)__hip_atomic_load(&w_mask[dig[i]], __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_WAVEFRONT)
+                          : 0ull;
+            __builtin_amdgcn_wave_barrier();
+            if (valid)
+                __hip_atomic_store(&w_mask[dig[i]], 0ull, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WAVEFRONT);
+            __builtin_amdgcn_wave_barrier();
+        }
         const uint32_t below = (uint32_t)__popcll(peers & lt);
         const uint32_t first = valid ? (uint32_t)(__ffsll((unsigned long long)peers) - 1) : lane;
         uint32_t base = 0;

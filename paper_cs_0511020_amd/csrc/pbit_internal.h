@@ -45,7 +45,7 @@ struct PassSched {
     uint32_t skip;      // every element has the same digit: the pass is the identity
     uint32_t in_kind;   // BufKind read
     uint32_t out_kind;  // BufKind written
-    uint32_t pad;
+    uint32_t ballot;    // rank by ballots (one digit holds over 1/16 of the elements)
 };
 
 // Device-side header at the start of the workspace (zeroed per sort).
