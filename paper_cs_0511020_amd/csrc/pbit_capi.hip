@@ -33,7 +33,7 @@ static uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 static size_t entry_bytes(uint32_t key_bytes) { return key_bytes == 8 ? 16 : 8; }
 static size_t node_bytes(uint32_t key_bytes) { return key_bytes == 8 ? 16 : 8; }
 static size_t pair_bytes(uint32_t key_bytes) { return key_bytes == 8 ? 12 : 8; }
-// Entries a level-0 walker keeps in registers (matches the device SegLen).
+// Entries a level-0 walker gathers in registers per burst (the device SegLen).
 static uint32_t reg_entries(uint32_t key_bytes) { return key_bytes == 8 ? 16 : 32; }
 
 // Entries stored per level-0 chain (a multiple of the walker's register

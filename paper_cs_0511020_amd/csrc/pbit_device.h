@@ -68,7 +68,7 @@ __device__ __forceinline__ uint32_t order_at(const OrderSrc& o, uint32_t kind, u
     return o.pair_idx[j * o.pair_words];
 }
 
-// Entries of a level-0 chain kept in registers by its walker.
+// Entries of a level-0 chain a walker gathers in registers before storing them.
 template <typename KeyT> struct SegLen { static constexpr uint32_t value = sizeof(KeyT) == 8 ? 16 : 32; };
 
 // Digit-pass tile: kPassBlock threads x PassItems items.

@@ -6,21 +6,23 @@
 //              walk step is one random access; the histograms of every K-bit
 //              pattern are counted here (order-free).
 //   walk0      sparse-ruler list ranking, level 0: every node whose index is a
-//              multiple of 16 (and the head) starts a segment; each lane walks
-//              its segment keeping up to 16 (key, node) entries in registers,
-//              then writes them as one block.
-//   walk_up    the same on the list of segments, recursively, until the list
+//              multiple of 16 (and the head) starts a chain; one lane walks
+//              each chain, gathering its (key, node) entries in register
+//              blocks that it stores to the chain's slot in bursts.
+//   walk_up    the same on the list of chains, recursively, until the list
 //              fits one workgroup.
 //   base       pointer jumping (Wyllie) in LDS over the last level.
 //   down       offsets flow back down the levels.
-//   unchain    segment contents are copied to list order.
+//   unchain    chain contents are copied to list order as (key, node) pairs;
+//              the rests of chains longer than their slot are walked again.
 //   schedule   per-pass digit bases; passes whose pattern is constant are
 //              skipped (the identity), the paper's "empty groups are omitted".
 //   digit pass stable K-bit split per pattern, least significant first:
-//              wave ballot ranking, LDS tile staging, decoupled look-back.
-//              Least-significant-first stable passes give the same order as
-//              the paper's most-significant-first recursion (both are the
-//              stable sort by the full key).
+//              per-wave ranking (LDS lane masks or ballots), LDS tile
+//              staging, decoupled look-back.  Least-significant-first stable
+//              passes give the same order as the paper's
+//              most-significant-first recursion (both are the stable sort by
+//              the full key).
 //   relink     next[order[j]] = order[j+1], the concatenation of Sec. 5.1.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -57,10 +59,10 @@ __device__ __forceinline__ bool list_shape_ok(const Header* hdr, uint32_t head)
 // wave slot as soon as a wave's chains are done.  A chain's record is
 // {successor chain or NIL, weight}; the chains form the list of level k + 1.
 //
-// Level 0 keeps the first SegLen (key, node) entries of its chain in
-// registers, stores the following ones straight to the chain's slot of
-// kChainCap entries, and records the node where a longer chain resumes; after
-// ranking, walk2 re-walks only those (rare) rests.
+// Level 0 stores the first `cap` (key, node) entries of its chain in the
+// chain's slot (SegLen at a time, through registers) and records the node
+// where a longer chain resumes; after ranking, unchain walks only those rests
+// again.
 // Levels >= 1 store nothing: their down pass walks the chain again.
 //
 // The walks assume every node has at most one predecessor; pack verifies it
