@@ -8,7 +8,7 @@ import pytest
 
 from paper_cs_0511020_amd import inputs
 
-from .gpu_util import NIL, check_properties, definition_order, gpu_sort, oracle_flags
+from .gpu_util import NIL, check_properties, definition_order, gpu_sort, oracle_flags, to_dev
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -119,6 +119,31 @@ def test_float_keys(oracle_mod, M):
             for flags in (4, 5):
                 say("float M=%d n=%d K=%d flags=%d" % (M, n, K, flags))
                 run_parity(oracle_mod, head, nxt, keys, K, flags=flags)
+
+
+def test_bfloat16_and_float16_dtypes(oracle_mod):
+    """torch half-precision dtypes select floating-point order in the binding;
+    bfloat16 is a sign-magnitude 16-bit pattern like binary16, so the oracle's
+    floating-point mode on the same bits defines the result."""
+    import torch
+    from paper_cs_0511020_amd.sorter import ListSorter
+    rng = inputs.rng_for(85)
+    n = 30011
+    nxt, head, _ = inputs.random_list(n, rng)
+    vals = torch.from_numpy(rng.standard_normal(n).astype(np.float32) * 1e3)
+    for dt in (torch.bfloat16, torch.float16):
+        kt = vals.to(dt)
+        kt[::7] = kt[3]
+        bits = kt.view(torch.int16).numpy().view(np.uint16)
+        nt = to_dev(nxt, torch)
+        for desc in (False, True):
+            nt.copy_(to_dev(nxt, torch))
+            say("%s descending=%s" % (dt, desc))
+            h = ListSorter().sort(head, nt, kt.to("cuda"), 8, descending=desc)
+            f = oracle_mod.FLAG_FLOAT | (oracle_mod.FLAG_DESCENDING if desc else 0)
+            eh, en = oracle_mod.sort_list(head, nxt, bits, 16, 8, flags=f)
+            assert h == eh
+            assert np.array_equal(nt.cpu().numpy().view(np.uint32), en)
 
 
 def test_special_layouts(oracle_mod):
