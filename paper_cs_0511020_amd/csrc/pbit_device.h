@@ -23,6 +23,16 @@ template <> struct __attribute__((aligned(16))) Entry<uint64_t> { uint64_t key; 
 
 template <typename KeyT> __device__ __forceinline__ KeyT entry_key(const Entry<KeyT>& e) { return (KeyT)e.key; }
 
+// Level-0 chain slots, planar: entry t of chain c sits in plane t / kPlane at
+// chain c's block of kPlane entries, so the first kPlane entries of all chains
+// (where most chains end: their mean length is 2^kLog0) are one dense array
+// that the walk fills and unchain reads nearly in order.
+constexpr uint32_t kPlane = 16;
+__device__ __forceinline__ size_t ent_at(uint32_t n_chains, uint32_t c, uint32_t t)
+{
+    return (size_t)(t / kPlane) * ((size_t)n_chains * kPlane) + (size_t)c * kPlane + (t % kPlane);
+}
+
 // (key, node) pair of the list-order buffers the digit passes stream through:
 // one 8-byte (16-byte for 64-bit keys) record per element, so a pass reads and
 // writes one contiguous run per digit instead of two half-length runs.
@@ -383,12 +393,12 @@ __global__ __launch_bounds__(256) void k_unchain(const uint2* __restrict__ chain
             walk_rest<KeyT>(nodes, own, (uint64_t)base + cap,
                             min<uint64_t>((uint64_t)base + full, (uint64_t)n), n, out);
     }
-    const Entry<KeyT>* b = ent + (size_t)c * cap;
+
     for (uint32_t t = lead; t < len; t += G) {
         const uint32_t pos = base + t;
         if (pos >= n)
             break;
-        const Entry<KeyT> e = b[t];
+        const Entry<KeyT> e = ent[ent_at(n_chains, c, t)];
         out[pos] = make_pair_kv<KeyT>(entry_key<KeyT>(e), e.idx);
     }
 }

@@ -130,7 +130,6 @@ __global__ __launch_bounds__(256) void k_fwalk0(const NodeRec<KeyT>* __restrict_
         hi = F.offsets[l + 1];
     }
     const uint32_t lmask = (1u << kLog0) - 1u;
-    Entry<KeyT>* b = ent + (size_t)c * cap;
     uint32_t cur = start, len = 0, nx = kNil;
     bool stop = false, bad = false;
     // register blocks of C entries, each stored in one burst (see k_walk0)
@@ -158,7 +157,7 @@ __global__ __launch_bounds__(256) void k_fwalk0(const NodeRec<KeyT>* __restrict_
 #pragma unroll
         for (uint32_t t = 0; t < C; t++)
             if (t < got)
-                b[len + t] = e[t];
+                ent[ent_at(n_static, c, len + t)] = e[t];
         len += got;
     }
     const uint32_t rest_from = stop ? kNil : cur;

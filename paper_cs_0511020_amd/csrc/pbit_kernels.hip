@@ -96,7 +96,6 @@ __global__ __launch_bounds__(256) void k_walk0(const NodeRec<KeyT>* __restrict__
         start = (uint32_t)s;
     }
     const uint32_t lmask = (1u << kLog0) - 1u;
-    Entry<KeyT>* b = ent + (size_t)c * cap;
     uint32_t cur = start, len = 0, nx = kNil;
     bool stop = false;
     // The slot fills C entries at a time: a block of steps keeps its entries
@@ -124,7 +123,7 @@ __global__ __launch_bounds__(256) void k_walk0(const NodeRec<KeyT>* __restrict__
 #pragma unroll
         for (uint32_t t = 0; t < C; t++)
             if (t < got)
-                b[len + t] = e[t];
+                ent[ent_at(n_static, c, len + t)] = e[t];
         len += got;
     }
     // beyond the slot the walk only counts; unchain walks this rest again
