@@ -409,32 +409,33 @@ __global__ __launch_bounds__(256) void k_unchain(const uint2* __restrict__ chain
 // empty groups), which ping-pong buffer it reads, and whether it must still
 // write keys (only while a later key pass runs).  Passes [0, key_passes) split
 // on key patterns, later passes on list ids.
-template <int RB>
-__global__ __launch_bounds__(256) void k_schedule(const uint32_t* __restrict__ hist,
-                                                  uint32_t* __restrict__ dbase, uint32_t passes,
-                                                  uint32_t key_passes, uint32_t n, Header* hdr)
+// The schedule as a block-level routine (256 threads, radix <= 256): its own
+// launch in the batched path, one extra block of the level-0 walk for one list.
+__device__ __forceinline__ void schedule_body(const uint32_t* __restrict__ hist,
+                                              uint32_t* __restrict__ dbase, uint32_t passes,
+                                              uint32_t key_passes, uint32_t n, uint32_t radix,
+                                              Header* hdr)
 {
-    constexpr uint32_t RADIX = 1u << RB;
-    __shared__ uint32_t s_v[RADIX];
+    __shared__ uint32_t s_v[256];
     __shared__ uint32_t s_skip[kMaxPasses];
     __shared__ uint32_t s_skew[kMaxPasses];
     const uint32_t tid = threadIdx.x;
     for (uint32_t p = 0; p < passes; p++) {
         uint32_t v = 0;
-        if (tid < RADIX) {
-            v = hist[p * RADIX + tid];
+        if (tid < radix) {
+            v = hist[p * radix + tid];
             s_v[tid] = v;
         }
         __syncthreads();
-        const int full = (tid < RADIX) && (v == n);
+        const int full = (tid < radix) && (v == n);
         const int any_full = __syncthreads_or(full);
         // a digit holding over 1/16 of the elements makes many lanes of a
         // wave share one LDS mask word; such passes rank by ballots instead
-        const int heavy = (tid < RADIX) && ((uint64_t)v * 16u > (uint64_t)n);
+        const int heavy = (tid < radix) && ((uint64_t)v * 16u > (uint64_t)n);
         const int any_heavy = __syncthreads_or(heavy);
         if (tid == 0) {
             uint32_t sum = 0;
-            for (uint32_t d = 0; d < RADIX; d++) {
+            for (uint32_t d = 0; d < radix; d++) {
                 const uint32_t x = s_v[d];
                 s_v[d] = sum;
                 sum += x;
@@ -443,8 +444,8 @@ __global__ __launch_bounds__(256) void k_schedule(const uint32_t* __restrict__ h
             s_skew[p] = any_heavy ? 1u : 0u;
         }
         __syncthreads();
-        if (tid < RADIX)
-            dbase[p * RADIX + tid] = s_v[tid];
+        if (tid < radix)
+            dbase[p * radix + tid] = s_v[tid];
         __syncthreads();
     }
     if (tid == 0) {
@@ -485,6 +486,14 @@ __global__ __launch_bounds__(256) void k_schedule(const uint32_t* __restrict__ h
         }
         hdr->final_kind = cur;
     }
+}
+
+template <int RB>
+__global__ __launch_bounds__(256) void k_schedule(const uint32_t* __restrict__ hist,
+                                                  uint32_t* __restrict__ dbase, uint32_t passes,
+                                                  uint32_t key_passes, uint32_t n, Header* hdr)
+{
+    schedule_body(hist, dbase, passes, key_passes, n, 1u << RB, hdr);
 }
 
 // ---------------------------------------------------------------- digit pass

@@ -75,9 +75,19 @@ __global__ __launch_bounds__(256) void k_walk0(const NodeRec<KeyT>* __restrict__
                                                uint2* __restrict__ chain_rec,
                                                Entry<KeyT>* __restrict__ ent,
                                                uint32_t* __restrict__ resume, uint32_t cap,
-                                               uint32_t* __restrict__ long_list, Header* hdr)
+                                               uint32_t* __restrict__ long_list, Header* hdr,
+                                               uint32_t walk_blocks,
+                                               const uint32_t* __restrict__ hist,
+                                               uint32_t* __restrict__ dbase, uint32_t passes,
+                                               uint32_t key_passes, uint32_t radix)
 {
     constexpr uint32_t C = SegLen<KeyT>::value;
+    if (blockIdx.x == walk_blocks) {
+        // one extra block: the pass schedule needs only pack's histograms, so
+        // it runs beside the walk instead of as a launch of its own
+        schedule_body(hist, dbase, passes, key_passes, n, radix, hdr);
+        return;
+    }
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_static)
         return;
@@ -342,11 +352,14 @@ template <typename KeyT>
 static hipError_t launch_walk0(const Plan& P, uint32_t head, char* ws, hipStream_t s)
 {
     const LevelPlan& L = P.lv[0];
-    hipLaunchKernelGGL((k_walk0<KeyT>), dim3((uint32_t)((L.n_static + 255) / 256)), dim3(256), 0,
-                       s, (const NodeRec<KeyT>*)(ws + P.o_nodes), (uint32_t)P.n, head,
+    const uint32_t walk_blocks = (uint32_t)((L.n_static + 255) / 256);
+    hipLaunchKernelGGL((k_walk0<KeyT>), dim3(walk_blocks + 1), dim3(256), 0, s,
+                       (const NodeRec<KeyT>*)(ws + P.o_nodes), (uint32_t)P.n, head,
                        (uint32_t)L.n_static, (uint2*)(ws + L.o_chain_rec),
                        (Entry<KeyT>*)(ws + L.o_ent), (uint32_t*)(ws + L.o_resume), L.cap,
-                       (uint32_t*)(ws + L.o_long), (Header*)(ws + P.o_header));
+                       (uint32_t*)(ws + L.o_long), (Header*)(ws + P.o_header), walk_blocks,
+                       (const uint32_t*)(ws + P.o_hist), (uint32_t*)(ws + P.o_dbase), P.passes,
+                       P.key_passes, P.radix);
     return hipGetLastError();
 }
 
@@ -450,10 +463,10 @@ static hipError_t enqueue_after_pack(const Plan& P, uint32_t head, char* out_bas
     if (e != hipSuccess)
         return e;
     switch (P.key_bytes) {
-    case 1: e = launch_passes<uint8_t, uint32_t>(P, ws, s, prof, LidMap{}); break;
-    case 2: e = launch_passes<uint16_t, uint32_t>(P, ws, s, prof, LidMap{}); break;
-    case 4: e = launch_passes<uint32_t, uint32_t>(P, ws, s, prof, LidMap{}); break;
-    default: e = launch_passes<uint64_t, uint32_t>(P, ws, s, prof, LidMap{}); break;
+    case 1: e = launch_passes<uint8_t, uint32_t>(P, ws, s, prof, LidMap{}, true); break;
+    case 2: e = launch_passes<uint16_t, uint32_t>(P, ws, s, prof, LidMap{}, true); break;
+    case 4: e = launch_passes<uint32_t, uint32_t>(P, ws, s, prof, LidMap{}, true); break;
+    default: e = launch_passes<uint64_t, uint32_t>(P, ws, s, prof, LidMap{}, true); break;
     }
     if (e != hipSuccess)
         return e;

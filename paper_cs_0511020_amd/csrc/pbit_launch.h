@@ -65,18 +65,20 @@ static hipError_t launch_pack(const Plan& P, const uint32_t* next, const void* k
 // passes on list ids (many-list sorts).
 template <typename KeyT, int RB, typename LW>
 static hipError_t launch_passes_rb(const Plan& P, char* ws, hipStream_t s, Prof* prof,
-                                   const LidMap& lm)
+                                   const LidMap& lm, bool scheduled)
 {
     constexpr int BLOCK = PassBlock<RB>::value;
     constexpr int ITEMS = PassItems<KeyT>::value;
     constexpr uint32_t RADIX = 1u << RB;
-    mark(prof, s, kStageSchedule);
-    hipLaunchKernelGGL((k_schedule<RB>), dim3(1), dim3(256), 0, s,
-                       (const uint32_t*)(ws + P.o_hist), (uint32_t*)(ws + P.o_dbase), P.passes,
-                       P.key_passes, (uint32_t)P.n, (Header*)(ws + P.o_header));
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
-        return e;
+    hipError_t e;
+    if (!scheduled) {
+        mark(prof, s, kStageSchedule);
+        hipLaunchKernelGGL((k_schedule<RB>), dim3(1), dim3(256), 0, s,
+                           (const uint32_t*)(ws + P.o_hist), (uint32_t*)(ws + P.o_dbase),
+                           P.passes, P.key_passes, (uint32_t)P.n, (Header*)(ws + P.o_header));
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+    }
     const uint32_t group = 8u * kPassChunk;
     const uint32_t grid = (uint32_t)((P.tiles + group - 1) / group * group);
     for (uint32_t p = 0; p < P.passes; p++) {
@@ -103,15 +105,16 @@ static hipError_t launch_passes_rb(const Plan& P, char* ws, hipStream_t s, Prof*
     return hipSuccess;
 }
 
+// scheduled: the schedule already ran (one extra block of the single-list walk)
 template <typename KeyT, typename LW>
 static hipError_t launch_passes(const Plan& P, char* ws, hipStream_t s, Prof* prof,
-                                const LidMap& lm)
+                                const LidMap& lm, bool scheduled = false)
 {
     switch (P.RB) {
-    case 1: return launch_passes_rb<KeyT, 1, LW>(P, ws, s, prof, lm);
-    case 2: return launch_passes_rb<KeyT, 2, LW>(P, ws, s, prof, lm);
-    case 4: return launch_passes_rb<KeyT, 4, LW>(P, ws, s, prof, lm);
-    default: return launch_passes_rb<KeyT, 8, LW>(P, ws, s, prof, lm);
+    case 1: return launch_passes_rb<KeyT, 1, LW>(P, ws, s, prof, lm, scheduled);
+    case 2: return launch_passes_rb<KeyT, 2, LW>(P, ws, s, prof, lm, scheduled);
+    case 4: return launch_passes_rb<KeyT, 4, LW>(P, ws, s, prof, lm, scheduled);
+    default: return launch_passes_rb<KeyT, 8, LW>(P, ws, s, prof, lm, scheduled);
     }
 }
 
