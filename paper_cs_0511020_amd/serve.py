@@ -81,6 +81,8 @@ class GpuExecutor:
         torch = self.torch
         M = batch[0].M
         L = len(batch)
+        if L == 1:
+            return self._launch_single(batch, batch_id)
         lens = np.array([r.n for r in batch], dtype=np.int64)
         offs = np.zeros(L + 1, dtype=np.int64)
         offs[1:] = np.cumsum(lens)
@@ -111,12 +113,41 @@ class GpuExecutor:
         return {"batch": batch, "end": end, "keep": (d_meta, d_heads, d_offs, ws),
                 "new_heads": new_heads, "status": status, "ws_bytes": wsb, "id": batch_id}
 
+    def _launch_single(self, batch, batch_id):
+        """A batch of one request takes the single-list call: fewer kernels
+        than the batched form, which pays off when requests arrive apart."""
+        torch = self.torch
+        r = batch[0]
+        stream = self.streams[self.next_stream]
+        self.next_stream = (self.next_stream + 1) % len(self.streams)
+        wsb = _lib.workspace_bytes(r.n, r.M, self.K)
+        with torch.cuda.stream(stream):
+            ws = torch.empty(wsb, dtype=torch.uint8, device=self.device)
+            res = torch.zeros(2, dtype=torch.int32, device=self.device)
+            st = self.lib.pbit_sort_list_async(r.head, r.next.data_ptr(), r.out.data_ptr(),
+                                               r.keys.data_ptr(), r.n, r.M, self.K, 0,
+                                               res.data_ptr(), ws.data_ptr(), wsb,
+                                               int(stream.cuda_stream))
+            if st != 0:
+                raise RuntimeError("single launch failed: " + _lib.status_string(st))
+            end = torch.cuda.Event(enable_timing=True)
+            end.record(stream)
+        return {"batch": batch, "end": end, "keep": (ws,), "single": res, "id": batch_id}
+
     def poll(self, h) -> bool:
         return h["end"].query()
 
     def finish(self, h):
         h["end"].synchronize()
         t = self.t0_event.elapsed_time(h["end"]) * 1e-3
+        if "single" in h:
+            head, st = (int(x) for x in h["single"].cpu().tolist())
+            r = h["batch"][0]
+            r.new_head = head & 0xFFFFFFFF
+            r.status = st
+            r.done = t
+            h["keep"] = None
+            return
         nh = h["new_heads"].cpu().numpy().view(np.uint32)
         st = int(h["status"].item())
         for r, x in zip(h["batch"], nh):
