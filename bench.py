@@ -538,8 +538,8 @@ def run_served(args, torch, np, inputs):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the sort runs on a single "
-              "device; no multi-GPU path exists); run with --gpus 1", file=sys.stderr)
+        print("bench.py: measures one GPU only (the sort runs on a single device; no "
+              "multi-GPU path exists); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
