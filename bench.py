@@ -46,8 +46,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=1 << 24,
                     help="nodes in the list the CPU oracle sorts once")
-    ap.add_argument("--c4", default="secondary", choices=["none", "secondary", "full"],
-                    help="batched section: 20 000 lists up to 2^16 (secondary) or 2^20 (full)")
+    ap.add_argument("--batched", default="short", choices=["none", "short", "long"],
+                    help="batched section: 20 000 lists of 16..2^16 nodes (short) or 16..2^20 (long)")
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--no-plain-compare", action="store_true",
                     help="skip the 20 000 single-list calls of the batched comparison")
@@ -119,7 +119,7 @@ def run_plain(args, lib, torch, np, inputs, bytemodel, EventPool):
         keys = inputs.uniform_keys(n, 64, rng)
         keys_d = torch.from_numpy(keys.view(np.int64)).to(dev)
     else:
-        keys = inputs.c2_keys(args.dist, n, rng)
+        keys = inputs.keys_by_distribution(args.dist, n, rng)
         keys_d = torch.from_numpy(keys.view(np.int32)).to(dev)
     next_in = torch.from_numpy(nxt.view(np.int32)).to(dev)
     next_out = torch.empty_like(next_in)
@@ -333,7 +333,7 @@ def run_batched(args, lib, torch, np, inputs, EventPool):
     one single-list call per list, same inputs, same stream."""
     from paper_cs_0511020_amd import _lib
     dev = torch.device("cuda:0")
-    hi = 20 if args.c4 == "full" else 16
+    hi = 20 if args.batched == "long" else 16
     rng = inputs.rng_for(4001)
     lengths = inputs.log_uniform_lengths(20000, 4, hi, rng, 16, 1 << hi)
     compare = not args.no_plain_compare
@@ -562,7 +562,7 @@ def main():
         torch.cuda.empty_cache()
 
     batched = None
-    if args.c4 != "none":
+    if args.batched != "none":
         batched = run_batched(args, lib, torch, np, inputs, EventPool)
     served = None
     if args.served != "none":
@@ -582,7 +582,7 @@ def main():
         seed = {"uniform": 2001, "zipf": 2002, "distinct8": 2003}[args.dist]
         crng = inputs.rng_for(seed + 100)
         cnxt, chead, _ = inputs.random_list(cn, crng)
-        ckeys = inputs.c2_keys(args.dist, cn, crng)
+        ckeys = inputs.keys_by_distribution(args.dist, cn, crng)
         oracle.build(force=False)
         tc0 = time.perf_counter()
         if args.M == 64:

@@ -123,7 +123,7 @@ def float_keys(n: int, M: int, rng: np.random.Generator, specials: bool = True) 
     return bits
 
 
-def c2_keys(dist: str, n: int, rng: np.random.Generator) -> np.ndarray:
+def keys_by_distribution(dist: str, n: int, rng: np.random.Generator) -> np.ndarray:
     if dist == "uniform":
         return uniform_keys(n, 32, rng)
     if dist == "zipf":

@@ -18,5 +18,5 @@ def test_help_lists_the_options():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 0
-    for opt in ("--gpus", "--steps", "--warmup", "--K", "--M", "--dist", "--c4", "--served"):
+    for opt in ("--gpus", "--steps", "--warmup", "--K", "--M", "--dist", "--batched", "--served"):
         assert opt in r.stdout

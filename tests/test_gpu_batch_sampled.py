@@ -1,4 +1,4 @@
-"""The batched form at the C4 shape the benchmark times: 20 000 lists with
+"""The batched form at the shape the benchmark times: 20 000 lists with
 log-uniform lengths in [16, 2^16] (about 1.6e8 nodes), uint32 keys, K = 8, one
 launch sequence.  A sample of lists (the longest, the shortest and random
 ones) is compared element by element with the oracle sorting each list alone;
@@ -20,12 +20,12 @@ def _gpu():
         pytest.skip("no GPU")
 
 
-def test_c4_secondary_sampled(oracle_mod):
+def test_20000_lists_sampled(oracle_mod):
     import torch
     from paper_cs_0511020_amd.sorter import ListsSorter
     rng = inputs.rng_for(4001)
     lengths = inputs.log_uniform_lengths(20000, 4, 16, rng, 16, 1 << 16)
-    print("C4 secondary: %d lists, %d nodes" % (len(lengths), int(lengths.sum())), flush=True)
+    print("20000 lists: %d nodes" % int(lengths.sum()), flush=True)
     d = inputs.slab_lists_device(lengths, seed=4001, M=32)
     nxt0 = d["next"].clone()
     offs = d["offsets_host"]

@@ -75,13 +75,13 @@ def test_single_list_batch_equals_plain(oracle_mod):
     check(oracle_mod, heads, offs, nxt, keys, 8)
 
 
-def test_c4_shape_reduced(oracle_mod):
+def test_many_lists_shape_reduced(oracle_mod):
     """Log-uniform lengths like the 20 000-list batch, scaled down."""
     rng = inputs.rng_for(4001)
     lengths = inputs.log_uniform_lengths(1500, 4, 14, rng, 16, 1 << 14)
     nxt, heads, offs = inputs.slab_lists(lengths, rng)
     keys = inputs.uniform_keys(nxt.shape[0], 32, rng)
-    say("c4 reduced total=%d" % nxt.shape[0])
+    say("many lists, reduced, total=%d" % nxt.shape[0])
     check(oracle_mod, heads, offs, nxt, keys, 8)
 
 

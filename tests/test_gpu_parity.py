@@ -51,8 +51,8 @@ def test_worked_example(oracle_mod):
 
 
 @pytest.mark.parametrize("K", [4, 8])
-def test_c1_uniform_u32_65536(oracle_mod, K):
-    say("C1 K=%d" % K)
+def test_uniform_u32_65536(oracle_mod, K):
+    say("65536 uniform u32 K=%d" % K)
     rng = inputs.rng_for(1001)
     n = 65536
     nxt, head, _ = inputs.random_list(n, rng)
@@ -86,12 +86,12 @@ def test_key_widths_and_patterns(oracle_mod, M, K):
 
 
 @pytest.mark.parametrize("dist", ["uniform", "zipf", "distinct8"])
-def test_c2_distributions_reduced(oracle_mod, dist):
-    say("C2 shape reduced %s" % dist)
+def test_key_distributions_reduced(oracle_mod, dist):
+    say("key distribution %s, reduced size" % dist)
     rng = inputs.rng_for({"uniform": 2001, "zipf": 2002, "distinct8": 2003}[dist])
     n = 1 << 18
     nxt, head, _ = inputs.random_list(n, rng)
-    keys = inputs.c2_keys(dist, n, rng)
+    keys = inputs.keys_by_distribution(dist, n, rng)
     for K in (4, 8):
         run_parity(oracle_mod, head, nxt, keys, K)
 
@@ -249,14 +249,14 @@ def test_sync_entry_point_in_place(oracle_mod):
 
 
 @pytest.mark.parametrize("dist", ["uniform", "zipf", "distinct8"])
-def test_c2_full_size_properties(oracle_mod, dist):
+def test_2e24_nodes_full_size(oracle_mod, dist):
     """n = 2^24 in the benchmark's configuration: the properties that fix
     the stable sort, plus the exact definition (numpy stable argsort)."""
-    say("C2 full %s" % dist)
+    say("n=2^24 %s" % dist)
     rng = inputs.rng_for({"uniform": 2001, "zipf": 2002, "distinct8": 2003}[dist])
     n = 1 << 24
     nxt, head, order = inputs.random_list(n, rng)
-    keys = inputs.c2_keys(dist, n, rng)
+    keys = inputs.keys_by_distribution(dist, n, rng)
     for K in (8, 4):
         h, st, got = gpu_sort(head, nxt, keys, K, inplace=False)
         assert st == 0
@@ -282,12 +282,12 @@ def test_head_on_chain_start_positions(oracle_mod, head):
 
 
 @pytest.mark.parametrize("K", [8, 4])
-def test_c3_u64_with_payload_full_size(oracle_mod, K):
+def test_2e26_u64_keys_with_payload(oracle_mod, K):
     """n = 2^26 nodes, uint64 keys, a uint64 payload per node: nodes never
     move, so walking the result must give the definition's (key, payload)
     sequence; checked by the properties that fix the stable sort and by
     numpy's stable argsort."""
-    say("C3 full K=%d" % K)
+    say("n=2^26 u64 with payload K=%d" % K)
     rng = inputs.rng_for(3001)
     n = 1 << 26
     nxt, head, order = inputs.random_list(n, rng)
