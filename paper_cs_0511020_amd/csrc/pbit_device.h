@@ -81,16 +81,21 @@ __device__ __forceinline__ uint32_t order_at(const OrderSrc& o, uint32_t kind, u
 // Entries of a level-0 chain a walker gathers in registers before storing them.
 template <typename KeyT> struct SegLen { static constexpr uint32_t value = sizeof(KeyT) == 8 ? 16 : 32; };
 
-// Digit-pass tile: kPassBlock threads x PassItems items.
-constexpr int kPassBlock = 1024;
-template <typename KeyT> struct PassItems { static constexpr int value = sizeof(KeyT) == 8 ? 8 : 16; };
-// Threads per digit-pass block for a pattern of RB bits.  Narrow patterns
-// need little LDS besides the tile, so a half-size tile lets two blocks share
-// a CU and overlap one's ranking with the other's memory traffic.
-#ifndef PBIT_NARROW_BLOCK
-#define PBIT_NARROW_BLOCK 512
-#endif
-template <int RB> struct PassBlock { static constexpr int value = RB <= 4 ? PBIT_NARROW_BLOCK : kPassBlock; };
+// Digit-pass tile shape: block threads x 8 items per thread.
+//  - Keys of up to 32 bits: 768 x 8 = 6144 elements.  The block needs 64.5 KB
+//    of LDS and at most 80 VGPRs (6 waves per SIMD), so two blocks share a
+//    CU and one block's ranking runs while the other waits on HBM.
+//  - 64-bit keys: 1024 x 8.  The 16-byte staging slots make the LDS tile
+//    128 KB, one block per CU whatever its width, so the widest block wins.
+//  - Patterns of 4 bits or fewer (either width): 512 x 8; the small digit
+//    tables leave room for two or more blocks per CU.
+// `waves` is the occupancy the kernel is compiled for (waves per SIMD),
+// which caps its registers.
+template <typename KeyT, int RB> struct PassShape {
+    static constexpr int block = RB <= 4 ? 512 : (sizeof(KeyT) == 8 ? 1024 : 768);
+    static constexpr int items = 8;
+    static constexpr int waves = block == 768 ? 6 : 4;
+};
 // Consecutive tiles given to one XCD in a row.  Work-groups go to the 8 XCDs
 // round-robin by block index, so block b takes tile
 //   (q / C) * 8C + (b % 8) * C + q % C,  q = b / 8, C = kPassChunk:
@@ -528,14 +533,10 @@ template <typename SKey> struct KV { SKey key; uint32_t idx; };
 constexpr uint32_t kSpinLimit = 4096;
 
 template <typename KeyT, int RB, int BLOCK, int ITEMS, typename LW, bool LID>
-__global__ __launch_bounds__(BLOCK, 4) void k_digit_pass(uint32_t pass, uint32_t shift, uint32_t n,
-                                                         Pair<KeyT>* __restrict__ pairsA,
-                                                         Pair<KeyT>* __restrict__ pairsB,
-                                                         uint32_t* __restrict__ idxA,
-                                                         uint32_t* __restrict__ idxB,
-                                                         const uint32_t* __restrict__ dbase,
-                                                         LW* __restrict__ look, Header* hdr,
-                                                         LidMap lm)
+__global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_pass(
+    uint32_t pass, uint32_t shift, uint32_t n, Pair<KeyT>* __restrict__ pairsA,
+    Pair<KeyT>* __restrict__ pairsB, uint32_t* __restrict__ idxA, uint32_t* __restrict__ idxB,
+    const uint32_t* __restrict__ dbase, LW* __restrict__ look, Header* hdr, LidMap lm)
 {
     using SKey = typename std::conditional<LID, uint32_t, KeyT>::type;
     using LK = Look<LW>;

@@ -37,8 +37,11 @@ namespace pbit {
 
 uint32_t pass_tile(uint32_t key_bytes, uint32_t rb)
 {
-    const uint32_t block = rb <= 4 ? (uint32_t)PassBlock<4>::value : (uint32_t)PassBlock<8>::value;
-    return block * (key_bytes == 8 ? 8u : 16u);
+    if (rb <= 4)
+        return key_bytes == 8 ? PassShape<uint64_t, 4>::block * PassShape<uint64_t, 4>::items
+                              : PassShape<uint32_t, 4>::block * PassShape<uint32_t, 4>::items;
+    return key_bytes == 8 ? PassShape<uint64_t, 8>::block * PassShape<uint64_t, 8>::items
+                          : PassShape<uint32_t, 8>::block * PassShape<uint32_t, 8>::items;
 }
 
 // A single list passes the in-degree check if exactly one next[] is NIL and

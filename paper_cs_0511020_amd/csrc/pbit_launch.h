@@ -67,8 +67,8 @@ template <typename KeyT, int RB, typename LW>
 static hipError_t launch_passes_rb(const Plan& P, char* ws, hipStream_t s, Prof* prof,
                                    const LidMap& lm, bool scheduled)
 {
-    constexpr int BLOCK = PassBlock<RB>::value;
-    constexpr int ITEMS = PassItems<KeyT>::value;
+    constexpr int BLOCK = PassShape<KeyT, RB>::block;
+    constexpr int ITEMS = PassShape<KeyT, RB>::items;
     constexpr uint32_t RADIX = 1u << RB;
     hipError_t e;
     if (!scheduled) {
