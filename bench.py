@@ -10,9 +10,16 @@ events on the stream the library launches on; the dominant stage's
 algorithmic bytes per launch over its mean launch time give the roofline
 figure.
 
-The same JSON line carries a "batched" section: 20 000 lists with log-uniform
-lengths sorted by one batched call (direct and replayed from a HIP graph),
-against the same lists sorted by 20 000 single-list calls.
+Beside the warm back-to-back rate (`value`) the line carries the same sort's
+latency when L2 and the last-level cache are flushed before it (a 1 GiB write
+on the stream, outside the sort's events), its HIP-graph replay time, and
+extras: binary32 keys, nodes stored as records, the backward-link repair and
+the paper's own input shape (10^7 nodes, keys below 2^15).
+
+A "batched" section sorts 20 000 lists with log-uniform lengths by one
+batched call (direct and replayed from a HIP graph), against the same lists
+sorted by 20 000 single-list calls; a "served" section runs the request
+server under Poisson arrivals.
 
 Prints ONE JSON line.
 """
@@ -54,6 +61,8 @@ def parse():
     ap.add_argument("--served", default="small", choices=["none", "small", "full"],
                     help="served section: 300 requests up to 2^20 nodes (small) or 2000 up "
                          "to 2^24 (full)")
+    ap.add_argument("--no-cold", action="store_true",
+                    help="skip the sorts timed after a 1 GiB cache flush")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the graph-replay timing of the single-list sort")
     ap.add_argument("--no-extras", action="store_true",
@@ -188,6 +197,28 @@ def run_plain(args, lib, torch, np, inputs, bytemodel, EventPool):
         ok = ok and bool(np.array_equal(next_out.cpu().numpy().view(np.uint32), got))
         del g
 
+    # cold: L2 and the last-level cache flushed (1 GiB written on the same
+    # stream) before each sort; the flush lies outside the sort's events
+    cold = None
+    if not args.no_cold:
+        scratch = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        cold_pools = [EventPool(max_ev) for _ in range(args.steps)]
+        cold_counts = []
+        for k in range(args.steps):
+            scratch.fill_(k & 0x7F)
+            cold_counts.append(run(cold_pools[k]))
+        torch.cuda.synchronize()
+        _, _, cold_lat = stage_table(lib, cold_pools, cold_counts)
+        cold = {"p10_ms": round(percentile(cold_lat, 0.10), 4),
+                "p50_ms": round(statistics.median(cold_lat), 4),
+                "p90_ms": round(percentile(cold_lat, 0.90), 4),
+                "Mnodes_s_at_p50": round(n / (statistics.median(cold_lat) * 1e-3) / 1e6, 1),
+                "flush_bytes": 1 << 30}
+        ok = ok and bool(np.array_equal(next_out.cpu().numpy().view(np.uint32), got))
+        for p in cold_pools:
+            p.close()
+        del scratch
+
     w = M // 8
     executed = launches.get("digit_pass", passes)
     path_bpn = bytemodel.path_bytes_per_node(w, executed)
@@ -219,7 +250,7 @@ def run_plain(args, lib, torch, np, inputs, bytemodel, EventPool):
         "value": n / (wall_ms * 1e-3) / 1e6, "wall_ms": wall_ms, "p50": p50, "p99": p99,
         "roofline": roofline, "stage_ms": stage_ms, "launches": launches, "correct": ok,
         "path_bpn": path_bpn, "path_frac": path_frac, "Keff": Keff, "src_hash": src_hash,
-        "graph_ms": graph_ms,
+        "graph_ms": graph_ms, "cold": cold,
     }
 
 
@@ -306,6 +337,40 @@ def run_extras(args, lib, torch, np, inputs, bytemodel):
     ok_aos = (ha == int(expa[0]) and bool(np.array_equal(ra[expa[:-1], 0], expa[1:]))
               and bool(np.array_equal(ra[:, 1:], rec[:, 1:])))
     del recs, pristine
+
+    # the paper's own input shape: 10^7 nodes, keys uniform below 2^15 (its
+    # rand() range); the patterns above bit 15 are constant, so their passes
+    # are skipped
+    pn = 10 ** 7
+    prng = inputs.rng_for(2401)
+    pnxt, phead, porder = inputs.random_list(pn, prng)
+    pkeys = prng.integers(0, 1 << 15, pn, dtype=np.uint32)
+    pnext_in = torch.from_numpy(pnxt.view(np.int32)).to(dev)
+    pnext_out = torch.empty_like(pnext_in)
+    pkeys_d = torch.from_numpy(pkeys.view(np.int32)).to(dev)
+    pexp = porder[np.argsort(pkeys[porder], kind="stable")]
+    paper_shape = {}
+    for pk in (8, 4):
+        pws_bytes = _lib.workspace_bytes(pn, 32, pk)
+        pws = torch.empty(pws_bytes, dtype=torch.uint8, device=dev)
+
+        def sort_paper():
+            st = _lib.sort_list_async(phead, pnext_in, pnext_out, pkeys_d, pn, 32, pk, 0, result,
+                                      pws, pws_bytes, stream)
+            if st != 0:
+                raise RuntimeError("paper-shape sort failed: " + _lib.status_string(st))
+
+        pms = timed(sort_paper)
+        hp = int(result[0].item()) & 0xFFFFFFFF
+        gotp = pnext_out.cpu().numpy().view(np.uint32)
+        okp = hp == int(pexp[0]) and bool(np.array_equal(gotp[pexp[:-1]], pexp[1:]))
+        skipped = sum(1 for sh in range(0, 32, pk) if sh >= 15)
+        paper_shape["K%d" % pk] = {"ms": round(pms, 4),
+                                   "Mnodes_per_s": round(pn / (pms * 1e-3) / 1e6, 1),
+                                   "passes": 32 // pk, "constant_patterns_skipped": skipped,
+                                   "correct": okp}
+        del pws
+    del pnext_in, pnext_out, pkeys_d
     rep_bytes = 8 * n + 4
     rep_gbs = rep_bytes / (rep_ms * 1e-3) / 1e9
     del ws, next_in
@@ -320,6 +385,8 @@ def run_extras(args, lib, torch, np, inputs, bytemodel):
                     "Mnodes_per_s": round(n / ((aos_ms - copy_ms) * 1e-3) / 1e6, 1),
                     "note": "time of a restore copy of the records subtracted",
                     "correct": ok_aos},
+        "paper_shape": dict(workload="single list n=10^7, u32 keys uniform on [0, 2^15), "
+                                     "random-permutation layout", **paper_shape),
         "repair_prev": {"workload": "backward links of the sorted %d-node list" % n,
                         "ms": round(rep_ms, 4), "bytes_per_node": 8,
                         "achieved_GBs": round(rep_gbs, 1),
@@ -617,6 +684,7 @@ def main():
         "latency_ms": {"p50": round(r["p50"], 4), "p99": round(r["p99"], 4)},
         "graph_replay_ms_per_step": (round(r["graph_ms"], 4) if r["graph_ms"] is not None
                                      else None),
+        "cold_latency_ms": r["cold"],
         "path_roofline": {"bytes_per_node": r["path_bpn"], "frac_at_p50": round(r["path_frac"], 4)},
         "stages_ms": {k: round(v, 4) for k, v in sorted(r["stage_ms"].items(), key=lambda x: -x[1])},
         "stage_launches": r["launches"],
