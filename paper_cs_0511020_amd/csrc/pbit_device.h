@@ -103,8 +103,10 @@ template <typename KeyT, int RB> struct PassShape {
 // partial cache lines where two tiles' runs meet merge in that XCD's L2
 // instead of being written back twice.  The look-back still follows tile
 // order; the tile a chunk's first tile waits on starts 8(C-1) blocks later,
-// well inside the blocks the chip holds at once.
-constexpr uint32_t kPassChunk = 8;
+// so a group of 8C blocks must fit on the chip at once: 128 blocks, against
+// 256 resident 64-bit-key blocks and 512 or more of the others.  (8, 16 and
+// 32 were measured; 16 was fastest or tied everywhere.)
+constexpr uint32_t kPassChunk = 16;
 
 __device__ __forceinline__ void set_error(int32_t* status, int32_t code)
 {
