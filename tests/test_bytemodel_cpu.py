@@ -1,0 +1,42 @@
+"""The algorithmic byte model behind every roofline figure.
+
+The path totals are pinned to the per-configuration table of the measurement
+plan (u32 and u64 keys, K = 8 and K = 4) and to the sum of its per-kernel
+terms: the first walk reads next (4 B), the second reads next and key and
+writes key and node (8 + 2w), every pass but the last reads and writes
+(key, node) (2(w + 4)), the last reads (key, node) and writes the node
+(w + 8), and the relink reads the order and writes next (8)."""
+import pytest
+
+from paper_cs_0511020_amd import bytemodel
+
+
+@pytest.mark.parametrize("w,passes,expected", [(4, 4, 88), (4, 8, 152), (8, 8, 220), (8, 16, 412)])
+def test_path_bytes_match_the_plan_table(w, passes, expected):
+    assert bytemodel.path_bytes_per_node(w, passes) == expected
+
+
+@pytest.mark.parametrize("w", [1, 2, 4, 8])
+@pytest.mark.parametrize("passes", [1, 2, 4, 8, 16, 64])
+def test_path_bytes_are_the_sum_of_the_kernel_terms(w, passes):
+    terms = [4, 8 + 2 * w] + [2 * (w + 4)] * (passes - 1) + [w + 8, 8]
+    assert bytemodel.path_bytes_per_node(w, passes) == sum(terms)
+
+
+def test_kernel_bytes_per_node():
+    # u32 keys: pack reads next + key and writes an 8-byte record; the walk
+    # reads a record and writes an entry; unchain reads an entry and writes a
+    # (key, node) pair; a pass moves a pair in and a pair out (the last one
+    # writes the node only); the relink reads a node and writes a link
+    assert bytemodel.kernel_bytes_per_node("pack", 4) == 16
+    assert bytemodel.kernel_bytes_per_node("walk0", 4) == 16
+    assert bytemodel.kernel_bytes_per_node("unchain", 4) == 16
+    assert bytemodel.kernel_bytes_per_node("digit_pass", 4) == 16
+    assert bytemodel.kernel_bytes_per_node("digit_pass", 4, last_pass=True) == 12
+    assert bytemodel.kernel_bytes_per_node("relink", 4) == 8
+    # u64 keys: 16-byte records and entries
+    assert bytemodel.kernel_bytes_per_node("pack", 8) == 28
+    assert bytemodel.kernel_bytes_per_node("walk0", 8) == 32
+    assert bytemodel.kernel_bytes_per_node("digit_pass", 8) == 24
+    with pytest.raises(KeyError):
+        bytemodel.kernel_bytes_per_node("nonesuch", 4)
