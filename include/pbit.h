@@ -73,8 +73,8 @@ enum {
  * Bytes of device workspace needed to sort a list of n nodes with M-bit keys
  * and K-bit patterns (K = 0: the library picks).  Returns 0 for arguments
  * pbit_sort_list_async would reject.  The workspace is O(n): for 32-bit
- * keys about 98 bytes per node up to 2^26 nodes and about 66 beyond (the
- * per-chain slots of the ranking shrink), more for 64-bit keys.
+ * keys about 94 bytes per node up to 2^26 nodes and about 62 beyond (the
+ * per-chain slots of the ranking shrink); about 174 for 64-bit keys.
  */
 size_t pbit_workspace_bytes(uint64_t n, uint32_t M, uint32_t K);
 
