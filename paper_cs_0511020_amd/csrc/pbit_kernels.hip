@@ -37,9 +37,7 @@ namespace pbit {
 
 uint32_t pass_tile(uint32_t key_bytes, uint32_t rb)
 {
-    if (rb <= 4)
-        return key_bytes == 8 ? PassShape<uint64_t, 4>::block * PassShape<uint64_t, 4>::items
-                              : PassShape<uint32_t, 4>::block * PassShape<uint32_t, 4>::items;
+    (void)rb;  // one shape for every pattern width
     return key_bytes == 8 ? PassShape<uint64_t, 8>::block * PassShape<uint64_t, 8>::items
                           : PassShape<uint32_t, 8>::block * PassShape<uint32_t, 8>::items;
 }

@@ -71,11 +71,10 @@ def test_sizes_ragged(oracle_mod, n):
     run_parity(oracle_mod, head, nxt, keys, 8, inplace=False)
 
 
-# Digit-pass tiles: 6144 elements for keys of up to 32 bits at K = 8, 8192
-# for 64-bit keys at K = 8, 4096 for patterns of 4 bits or fewer.  Lists of
-# one element either side of one, two and three tiles.
+# Digit-pass tiles: 6144 elements for keys of up to 32 bits, 8192 for 64-bit
+# keys.  Lists of one element either side of one, two and three tiles.
 @pytest.mark.parametrize("M,K,tile", [(32, 8, 6144), (16, 8, 6144), (64, 8, 8192),
-                                      (32, 4, 4096), (64, 4, 4096)])
+                                      (32, 4, 6144), (64, 4, 8192), (8, 2, 6144)])
 def test_pass_tile_boundaries(oracle_mod, M, K, tile):
     for n in (tile - 1, tile, tile + 1, 2 * tile - 1, 2 * tile, 2 * tile + 1, 3 * tile + 5):
         say("tile boundary M=%d K=%d n=%d" % (M, K, n))
