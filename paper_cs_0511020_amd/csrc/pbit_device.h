@@ -81,20 +81,22 @@ __device__ __forceinline__ uint32_t order_at(const OrderSrc& o, uint32_t kind, u
 // Entries of a level-0 chain a walker gathers in registers before storing them.
 template <typename KeyT> struct SegLen { static constexpr uint32_t value = sizeof(KeyT) == 8 ? 16 : 32; };
 
-// Digit-pass tile shape: block threads x 8 items per thread, for every
-// pattern width.
-//  - Keys of up to 32 bits: 768 x 8 = 6144 elements.  The block needs at
-//    most 64.5 KB of LDS and 80 VGPRs (6 waves per SIMD), so two blocks share
-//    a CU and one block's ranking runs while the other waits on HBM.
+// Digit-pass tile shape (block threads x items per thread), the same for
+// every pattern width.  The pass is latency-bound, so the shape is chosen for
+// resident waves:
+//  - Keys of up to 32 bits: 1024 x 6 = 6144 elements.  The block needs
+//    68.6 KB of LDS and at most 64 VGPRs (8 waves per SIMD), so two blocks
+//    share a CU: 32 waves, each ranking while others wait on HBM.  (768 x 8,
+//    the same tile at 24 waves per CU, was 6 % slower; 1024 x 5 and 896 x 6
+//    slower still.)
 //  - 64-bit keys: 1024 x 8.  The 16-byte staging slots make the LDS tile
 //    128 KB, one block per CU whatever its width, so the widest block wins.
-// (Measured against 512 x 8 at K = 4: 10 % faster per pass for 32-bit keys,
-// 20 % for 64-bit keys.)  `waves` is the occupancy the kernel is compiled
-// for (waves per SIMD), which caps its registers.
+// `waves` is the occupancy the kernel is compiled for (waves per SIMD),
+// which caps its registers.
 template <typename KeyT, int RB> struct PassShape {
-    static constexpr int block = sizeof(KeyT) == 8 ? 1024 : 768;
-    static constexpr int items = 8;
-    static constexpr int waves = block == 768 ? 6 : 4;
+    static constexpr int block = 1024;
+    static constexpr int items = sizeof(KeyT) == 8 ? 8 : 6;
+    static constexpr int waves = sizeof(KeyT) == 8 ? 4 : 8;
 };
 // Consecutive tiles given to one XCD in a row.  Work-groups go to the 8 XCDs
 // round-robin by block index, so block b takes tile
