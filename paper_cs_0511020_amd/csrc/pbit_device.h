@@ -231,6 +231,11 @@ template <typename KeyT> struct GatherSrc {
     }
 };
 
+// Sources whose next[] and keys[] can be read four nodes at a time with
+// 16-byte loads (when both arrays are 16-byte aligned).
+template <class Src> struct Loads4 { static constexpr bool value = false; };
+template <> struct Loads4<DirectSrc<uint32_t>> { static constexpr bool value = true; };
+
 // Node records, the count of every pattern value of every key pass, the NIL
 // count and the hash sums sum h(next) - sum h(i).
 template <typename KeyT, int RB, class Src>
@@ -248,11 +253,9 @@ __global__ __launch_bounds__(256) void k_pack(Src src, uint32_t n, KeyT float_se
     bool bad = false;
     uint64_t h1 = 0, h2 = 0;
     uint32_t nils = 0;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += stride) {
-        uint32_t nx;
-        KeyT k;
-        src.load(i, n, nx, k, bad);
+    // one node: key transform, hashes, NIL count, histograms; returns the
+    // transformed key (the caller writes the record)
+    auto take = [&](size_t i, uint32_t nx, KeyT k) -> KeyT {
         // Floating-point keys (sign-magnitude): a negative pattern is inverted
         // whole, a non-negative one gets its sign bit set, so unsigned order of
         // the result is the numeric order.  float_sel is all ones or zero.
@@ -270,15 +273,45 @@ __global__ __launch_bounds__(256) void k_pack(Src src, uint32_t n, KeyT float_se
         }
         h1 -= mix64(i + 1ull, kHashK1);
         h2 -= mix64(i + 1ull, kHashK2);
+        for (uint32_t p = 0; p < passes; p++) {
+            const uint32_t d = (uint32_t)(k >> (p * RB)) & (RADIX - 1u);
+            atomicAdd(&s_hist[p * RADIX + d], 1u);
+        }
+        return k;
+    };
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t gid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    size_t first = 0;  // nodes below this index were taken four at a time
+    if constexpr (Loads4<Src>::value) {
+        if ((((uintptr_t)src.next | (uintptr_t)src.keys) & 15u) == 0) {
+            const size_t quads = n / 4;
+            for (size_t q = gid; q < quads; q += stride) {
+                const uint4 a = ((const uint4*)src.next)[q];
+                const uint4 b = ((const uint4*)src.keys)[q];
+                const uint32_t nx[4] = {a.x, a.y, a.z, a.w};
+                uint32_t k[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    bad |= (nx[j] != kNil) && (nx[j] >= n);
+                    k[j] = take(4 * q + j, nx[j], k[j]);
+                }
+                uint4* out = (uint4*)(nodes + 4 * q);
+                out[0] = make_uint4(nx[0], k[0], nx[1], k[1]);
+                out[1] = make_uint4(nx[2], k[2], nx[3], k[3]);
+            }
+            first = quads * 4;
+        }
+    }
+    for (size_t i = first + gid; i < n; i += stride) {
+        uint32_t nx;
+        KeyT k;
+        src.load(i, n, nx, k, bad);
+        k = take(i, nx, k);
         NodeRec<KeyT> r;
         r.next = nx;
         r.key = k;
         if constexpr (sizeof(KeyT) == 8) r.pad = 0;
         nodes[i] = r;
-        for (uint32_t p = 0; p < passes; p++) {
-            const uint32_t d = (uint32_t)(k >> (p * RB)) & (RADIX - 1u);
-            atomicAdd(&s_hist[p * RADIX + d], 1u);
-        }
     }
     if (bad)
         set_error(&hdr->status, PBIT_EMALFORMED);
