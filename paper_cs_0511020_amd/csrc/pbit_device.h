@@ -360,6 +360,10 @@ __global__ __launch_bounds__(256) void k_pack(Src src, uint32_t n, KeyT float_se
 // thread.
 constexpr uint32_t kLongBlocks = kLongListMax / 256;
 constexpr uint32_t kUnchainThreads = 1u << kLog0;
+// Entries one unchain thread copies per step: two 8-byte entries (one 16-byte
+// load) for keys of up to 32 bits, one 16-byte entry for 64-bit keys.  (Two
+// beat one by 22 % and four by 16 %.)
+template <typename KeyT> struct UnchainPer { static constexpr uint32_t value = sizeof(KeyT) == 8 ? 1 : 2; };
 
 // End of a level-0 walk: where the rest of a long chain is walked from.
 // long_list holds {chain, resume node} pairs for the early blocks; resume[c]
@@ -405,7 +409,9 @@ __global__ __launch_bounds__(256) void k_unchain(const uint2* __restrict__ chain
                                                  const uint32_t* __restrict__ long_list,
                                                  Pair<KeyT>* __restrict__ out, Header* hdr)
 {
-    constexpr uint32_t G = kUnchainThreads;  // threads per chain (the mean chain length)
+    constexpr uint32_t PER = UnchainPer<KeyT>::value;
+    // threads per chain: together they copy the mean chain length per step
+    constexpr uint32_t G = kUnchainThreads / PER;
     if (hdr->status != 0)
         return;
     if (blockIdx.x < kLongBlocks) {
@@ -436,12 +442,29 @@ __global__ __launch_bounds__(256) void k_unchain(const uint2* __restrict__ chain
                             min<uint64_t>((uint64_t)base + full, (uint64_t)n), n, out);
     }
 
-    for (uint32_t t = lead; t < len; t += G) {
+    for (uint32_t t = lead * PER; t < len; t += kUnchainThreads) {
         const uint32_t pos = base + t;
         if (pos >= n)
             break;
-        const Entry<KeyT> e = ent[ent_at(n_chains, c, t)];
-        out[pos] = make_pair_kv<KeyT>(entry_key<KeyT>(e), e.idx);
+        if constexpr (PER > 1) {
+            // t is a multiple of PER, so entries t .. t + PER - 1 are adjacent
+            // in one plane: PER / 2 aligned 16-byte loads
+            const uint4* src = (const uint4*)&ent[ent_at(n_chains, c, t)];
+            uint4 v[PER / 2];
+#pragma unroll
+            for (uint32_t h = 0; h < PER / 2; h++)
+                v[h] = src[h];
+#pragma unroll
+            for (uint32_t j = 0; j < PER; j++) {
+                const uint4 w = v[j / 2];
+                const uint32_t key = (j & 1) ? w.z : w.x, idx = (j & 1) ? w.w : w.y;
+                if (j == 0 || (t + j < len && pos + j < n))
+                    out[pos + j] = make_pair_kv<KeyT>((KeyT)key, idx);
+            }
+        } else {
+            const Entry<KeyT> e = ent[ent_at(n_chains, c, t)];
+            out[pos] = make_pair_kv<KeyT>(entry_key<KeyT>(e), e.idx);
+        }
     }
 }
 

@@ -132,7 +132,7 @@ template <typename KeyT>
 static hipError_t launch_unchain(const Plan& P, char* ws, hipStream_t s, Prof* prof)
 {
     const LevelPlan& L = P.lv[0];
-    const uint64_t threads = L.n_static * kUnchainThreads;
+    const uint64_t threads = L.n_static * (kUnchainThreads / UnchainPer<KeyT>::value);
     mark(prof, s, kStageUnchain);
     hipLaunchKernelGGL((k_unchain<KeyT>), dim3(kLongBlocks + (uint32_t)((threads + 255) / 256)),
                        dim3(256), 0, s, (const uint2*)(ws + L.o_chain_rec),
