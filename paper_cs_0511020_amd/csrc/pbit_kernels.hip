@@ -209,7 +209,9 @@ __global__ __launch_bounds__(256) void k_walk_up(const uint2* __restrict__ recs,
 // ---------------------------------------------------------------- base
 // Pointer jumping (Wyllie) in LDS: suffix weights from every element to the
 // end of the list, then offset = total - suffix.  The list must end in NIL
-// from element 0 and cover exactly n nodes.
+// from element 0 and cover exactly n nodes.  Each element is one 8-byte LDS
+// word (pointer, weight); a thread keeps its own elements in registers, so a
+// round is one dependent read and one write per element.
 constexpr int kBaseThreads = 1024;
 constexpr int kBasePer = kBaseMax / kBaseThreads;
 
@@ -217,8 +219,7 @@ __global__ __launch_bounds__(kBaseThreads) void k_base(const uint2* __restrict__
                                                        uint32_t n_total,
                                                        uint32_t* __restrict__ offn, Header* hdr)
 {
-    __shared__ uint32_t s_ptr[kBaseMax];
-    __shared__ uint32_t s_val[kBaseMax];
+    __shared__ uint2 s_pv[kBaseMax];  // (pointer, suffix weight so far)
     __shared__ int s_bad;
     if (hdr->status != 0)
         return;
@@ -226,6 +227,8 @@ __global__ __launch_bounds__(kBaseThreads) void k_base(const uint2* __restrict__
     const int tid = threadIdx.x;
     if (tid == 0)
         s_bad = 0;
+    uint2 own[kBasePer];
+#pragma unroll
     for (int j = 0; j < kBasePer; j++) {
         const uint32_t i = tid + j * kBaseThreads;
         uint32_t p = kNil, v = 0;
@@ -236,48 +239,41 @@ __global__ __launch_bounds__(kBaseThreads) void k_base(const uint2* __restrict__
                 v = r.y;
             }
         }
-        s_ptr[i] = p;
-        s_val[i] = v;
+        own[j] = make_uint2(p, v);
+        s_pv[i] = own[j];
     }
     __syncthreads();
     int rounds = 1;
     while ((1u << (rounds - 1)) < m)
         rounds++;
     for (int r = 0; r < rounds; r++) {
-        uint32_t np[kBasePer], nv[kBasePer];
 #pragma unroll
         for (int j = 0; j < kBasePer; j++) {
-            const uint32_t i = tid + j * kBaseThreads;
-            uint32_t p = s_ptr[i];
-            uint32_t v = s_val[i];
-            if (p != kNil) {
-                v += s_val[p];
-                p = s_ptr[p];
+            if (own[j].x != kNil) {
+                const uint2 q = s_pv[own[j].x];
+                own[j] = make_uint2(q.x, own[j].y + q.y);
             }
-            np[j] = p;
-            nv[j] = v;
         }
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < kBasePer; j++) {
-            const uint32_t i = tid + j * kBaseThreads;
-            s_ptr[i] = np[j];
-            s_val[i] = nv[j];
-        }
+        for (int j = 0; j < kBasePer; j++)
+            s_pv[tid + j * kBaseThreads] = own[j];
         __syncthreads();
     }
-    const uint32_t total = s_val[0];
-    if (tid == 0 && (m == 0 || s_ptr[0] != kNil || total != n_total)) {
+    const uint2 head = s_pv[0];
+    const uint32_t total = head.y;
+    if (tid == 0 && (m == 0 || head.x != kNil || total != n_total)) {
         s_bad = 1;
         set_error(&hdr->status, PBIT_EMALFORMED);
     }
     __syncthreads();
     if (s_bad)
         return;
+#pragma unroll
     for (int j = 0; j < kBasePer; j++) {
         const uint32_t i = tid + j * kBaseThreads;
         if (i < m)
-            offn[i] = total - s_val[i];
+            offn[i] = total - own[j].y;
     }
 }
 
