@@ -60,6 +60,18 @@ def test_workspace_bytes_shapes(lib):
     assert 1.8 < b / a < 2.2
 
 
+def test_workspace_sizes_match_the_header(lib):
+    # include/pbit.h: about 94 bytes per node for 32-bit keys up to 2^26
+    # nodes, about 62 beyond, about 174 for 64-bit keys
+    per = lambda n, M, K: _lib.workspace_bytes(n, M, K) / n  # noqa: E731
+    assert 90 < per(1 << 24, 32, 8) < 98
+    assert 90 < per(1 << 26, 32, 8) < 98
+    assert 58 < per(1 << 28, 32, 8) < 66
+    assert 168 < per(1 << 26, 64, 8) < 180
+    # the batched form: about 63 bytes per node at the 20 000-list batch
+    assert 58 < _lib.lists_workspace_bytes(1_944_927_695, 20000, 32, 8) / 1_944_927_695 < 68
+
+
 def _call(lib, head=0, nxt=0x1000, nout=0x1000, keys=0x1000, n=8, M=32, K=4, flags=0,
           res=0x2000, ws=0x100000, ws_bytes=1 << 40):
     return lib.pbit_sort_list_async(head, nxt, nout, keys, n, M, K, flags, res, ws, ws_bytes,
