@@ -18,5 +18,6 @@ def test_help_lists_the_options():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 0
-    for opt in ("--gpus", "--steps", "--warmup", "--K", "--M", "--dist", "--batched", "--served"):
+    for opt in ("--gpus", "--steps", "--warmup", "--K", "--M", "--dist", "--batched", "--served",
+                "--no-cold", "--no-graph", "--no-extras"):
         assert opt in r.stdout
