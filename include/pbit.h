@@ -227,6 +227,18 @@ int pbit_sort_list_aos_async(uint32_t head, void *nodes, uint64_t stride, uint32
 int pbit_repair_prev_async(const uint32_t *d_heads, uint32_t num_lists, const uint32_t *next,
                            uint32_t *prev, uint64_t n, int32_t *d_status, void *stream);
 
+/*
+ * Diagnostic: how long a digit pass's tile waits on a predecessor tile that
+ * has not yet published its digit counts (decoupled look-back) before it
+ * counts that predecessor's digits in the pass input itself.  `sleeps` is the
+ * number of short sleeps per predecessor (default 4096); 0 makes every such
+ * tile take the counting path at once.  The result is the same either way;
+ * the setting exists so that tests can run the counting path on purpose.  It
+ * is process-wide, applies to sorts queued after the call, and returns the
+ * previous value.
+ */
+uint32_t pbit_set_lookback_spin_limit(uint32_t sleeps);
+
 /* Human-readable text for a status code. */
 const char *pbit_status_string(int code);
 

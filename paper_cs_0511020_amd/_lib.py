@@ -55,6 +55,7 @@ _SIGNATURES = {
     "pbit_repair_prev_async": (ctypes.c_int, [
         ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
         ctypes.c_void_p, ctypes.c_void_p]),
+    "pbit_set_lookback_spin_limit": (ctypes.c_uint32, [ctypes.c_uint32]),
     "pbit_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "pbit_version": (ctypes.c_char_p, []),
 }
@@ -85,6 +86,12 @@ def status_string(code: int) -> str:
 
 def version() -> str:
     return load().pbit_version().decode()
+
+
+def set_lookback_spin_limit(sleeps: int) -> int:
+    """Look-back wait bound for digit passes queued from now on (diagnostic;
+    0 sends every waiting tile down its counting path).  Returns the old one."""
+    return int(load().pbit_set_lookback_spin_limit(int(sleeps)))
 
 
 def workspace_bytes(n: int, M: int, K: int = 0) -> int:
@@ -123,6 +130,17 @@ def sort_lists(heads, offsets, num_lists: int, total: int, next_in, next_out, ke
         _ptr(heads), _ptr(offsets), int(num_lists), int(total), _ptr(next_in), _ptr(next_out),
         _ptr(keys), int(M), int(K), int(flags), _ptr(new_heads), _ptr(status), _ptr(ws),
         int(ws_bytes), _stream_handle(stream)))
+
+
+def sort_lists_gather(heads, offsets, num_lists: int, total: int, next_in_ptrs, next_out_ptrs,
+                      key_ptrs, M: int, K: int, flags: int, new_heads, status, ws,
+                      ws_bytes: int, stream=None) -> int:
+    """Raw C-ABI call of the gather form: the three pointer tables are device
+    int64 tensors holding each list's array addresses."""
+    return int(load().pbit_sort_lists_gather(
+        _ptr(heads), _ptr(offsets), int(num_lists), int(total), _ptr(next_in_ptrs),
+        _ptr(next_out_ptrs), _ptr(key_ptrs), int(M), int(K), int(flags), _ptr(new_heads),
+        _ptr(status), _ptr(ws), int(ws_bytes), _stream_handle(stream)))
 
 
 def sort_list(head: int, next_, keys, M: int, K: int = 0) -> int:

@@ -4,6 +4,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <atomic>
 #include <mutex>
 
 #include "pbit.h"
@@ -25,6 +26,9 @@ hipError_t enqueue_sort_lists(const Plan& P, const uint32_t* heads, const uint64
 hipError_t enqueue_repair_prev(const uint32_t* heads, uint32_t num_lists, const uint32_t* next,
                                uint32_t* prev, uint32_t n, int32_t* status, hipStream_t s);
 uint32_t pass_tile(uint32_t key_bytes, uint32_t rb);
+
+// Look-back spin bound given to every digit pass queued from now on.
+static std::atomic<uint32_t> g_spin_limit{kSpinLimit};
 
 static size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
@@ -80,6 +84,7 @@ static bool plan_common(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, uint
     if (P->passes > (uint32_t)kMaxPasses)
         return false;
     P->flags = flags;
+    P->spin_limit = g_spin_limit.load(std::memory_order_relaxed);
     P->key_bytes = M / 8;
     P->tile = pass_tile(P->key_bytes, P->RB);
     P->tiles = (uint32_t)ceil_div(n ? n : 1, P->tile);
@@ -490,6 +495,11 @@ extern "C" int pbit_sort_lists_profiled(const uint32_t* d_heads, const uint64_t*
                                    &prof);
     *n_recorded = prof.count;
     return st;
+}
+
+extern "C" uint32_t pbit_set_lookback_spin_limit(uint32_t sleeps)
+{
+    return g_spin_limit.exchange(sleeps, std::memory_order_relaxed);
 }
 
 extern "C" const char* pbit_status_string(int code)

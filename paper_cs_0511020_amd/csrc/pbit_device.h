@@ -218,6 +218,14 @@ template <typename KeyT> struct GatherSrc {
         const uint64_t off = lm.offsets[l];
         const uint64_t len = lm.offsets[l + 1] - off;
         const uint64_t loc = i - off;
+        if (i < off || loc >= len) {
+            // the node -> list table does not cover node i: the batch is not
+            // what k_fprep validated, so flag it instead of reading
+            nx = kNil;
+            k = 0;
+            bad = true;
+            return;
+        }
         const uint32_t nl = ((const uint32_t*)next_ptrs[l])[loc];
         k = ((const KeyT*)key_ptrs[l])[loc];
         if (nl == kNil) {
@@ -246,6 +254,10 @@ __global__ __launch_bounds__(256) void k_pack(Src src, uint32_t n, KeyT float_se
 {
     constexpr uint32_t RADIX = 1u << RB;
     extern __shared__ uint32_t s_hist[];  // passes * RADIX
+    // a batch whose slabs or heads failed validation is not read at all (the
+    // node -> list table of a gather batch is incomplete then)
+    if (__syncthreads_or(hdr->status != 0))
+        return;
     const uint32_t nbins = passes * RADIX;
     for (uint32_t i = threadIdx.x; i < nbins; i += blockDim.x)
         s_hist[i] = 0;
@@ -590,13 +602,13 @@ template <> struct Look<uint64_t> {
 
 template <typename SKey> struct KV { SKey key; uint32_t idx; };
 
-constexpr uint32_t kSpinLimit = 4096;
 
 template <typename KeyT, int RB, int BLOCK, int ITEMS, typename LW, bool LID>
 __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_pass(
     uint32_t pass, uint32_t shift, uint32_t n, Pair<KeyT>* __restrict__ pairsA,
     Pair<KeyT>* __restrict__ pairsB, uint32_t* __restrict__ idxA, uint32_t* __restrict__ idxB,
-    const uint32_t* __restrict__ dbase, LW* __restrict__ look, Header* hdr, LidMap lm)
+    const uint32_t* __restrict__ dbase, LW* __restrict__ look, Header* hdr, LidMap lm,
+    uint32_t spin_limit)
 {
     using SKey = typename std::conditional<LID, uint32_t, KeyT>::type;
     using LK = Look<LW>;
@@ -781,7 +793,7 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
                 const LW v = ld_agent(&look[(size_t)j * RADIX + d]);
                 const LW f = v & ~LK::MASK;
                 if (f == 0) {
-                    if (++spins <= kSpinLimit) {
+                    if (++spins <= spin_limit) {
                         __builtin_amdgcn_s_sleep(1);
                         continue;
                     }

@@ -28,6 +28,11 @@ constexpr int kMaxLevels = 12;
 // blocks take (each further one is walked by its own chain's group).
 constexpr uint32_t kLongListMax = 16 * 256;
 constexpr int kMaxPasses = 96;
+// Sleeps a digit pass's look-back waits on one predecessor tile before it
+// counts that tile's digit itself (default; pbit_set_lookback_spin_limit
+// changes it, 0 makes every tile whose predecessor has not published yet
+// take that fallback at once).
+constexpr uint32_t kSpinLimit = 4096;
 
 // Lookback words: 2 flag bits + 30-bit count.
 constexpr uint32_t kFlagAgg = 1u << 30;
@@ -94,6 +99,7 @@ struct Plan {
     uint32_t M, K, RB, radix, passes, flags, key_bytes;
     uint32_t tile, tiles;
     uint32_t key_passes;  // passes on key patterns; the rest split on list ids
+    uint32_t spin_limit;  // look-back sleeps on one predecessor before the fallback
     uint32_t num_lists;   // many-list sorts
     uint32_t log_block;   // many-list sorts: node block size of the list table
     int levels;           // walk levels; the base ranks level `levels`

@@ -66,9 +66,13 @@ __device__ __forceinline__ bool list_shape_ok(const Header* hdr, uint32_t head)
 // again.
 // Levels >= 1 store nothing: their down pass walks the chain again.
 //
-// The walks assume every node has at most one predecessor; pack verifies it
-// (hash sums over next[]), so every node is walked once in total and a bad
-// list is rejected before any walk starts.
+// The walks assume every node has at most one predecessor.  Pack checks it
+// with two 64-bit hash sums over next[] (probabilistic: a malformed list
+// passes only if both sums collide), so every node is walked once and a bad
+// list is almost always rejected before any walk starts.  Safety does not
+// rest on that check: every walk is bounded by n steps, every index is
+// checked against n before use, and the base verifies that the chain lengths
+// add up to n from the head.
 
 template <typename KeyT>
 __global__ __launch_bounds__(256) void k_walk0(const NodeRec<KeyT>* __restrict__ nodes, uint32_t n,

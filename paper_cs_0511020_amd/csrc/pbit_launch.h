@@ -90,13 +90,13 @@ static hipError_t launch_passes_rb(const Plan& P, char* ws, hipStream_t s, Prof*
                                dim3(BLOCK), 0, s, p, p * RB, (uint32_t)P.n,
                                (Pair<KeyT>*)(ws + P.o_pairsA), (Pair<KeyT>*)(ws + P.o_pairsB),
                                (uint32_t*)(ws + P.o_idxA), (uint32_t*)(ws + P.o_idxB), dbase, look,
-                               (Header*)(ws + P.o_header), lm);
+                               (Header*)(ws + P.o_header), lm, P.spin_limit);
         } else {
             hipLaunchKernelGGL((k_digit_pass<KeyT, RB, BLOCK, ITEMS, LW, true>), dim3(grid),
                                dim3(BLOCK), 0, s, p, (p - P.key_passes) * RB, (uint32_t)P.n,
                                (Pair<KeyT>*)(ws + P.o_pairsA), (Pair<KeyT>*)(ws + P.o_pairsB),
                                (uint32_t*)(ws + P.o_idxA), (uint32_t*)(ws + P.o_idxB), dbase, look,
-                               (Header*)(ws + P.o_header), lm);
+                               (Header*)(ws + P.o_header), lm, P.spin_limit);
         }
         e = hipGetLastError();
         if (e != hipSuccess)

@@ -35,6 +35,27 @@ def key_flags(keys: torch.Tensor, descending: bool, signed: bool) -> int:
     return flags
 
 
+def _retire(ws, streams):
+    """Before a workspace grown on demand is dropped: sorts queued on side
+    streams may still use it, so the caching allocator must not hand its
+    memory out again before those streams pass this point."""
+    if ws is not None:
+        for s in streams:
+            ws.record_stream(s)
+    streams.clear()
+
+
+def _note_stream(streams, stream, *tensors):
+    """A call queued on a stream other than the current one: remember the
+    stream for the workspace and keep the result words alive for it."""
+    if stream is None or stream == torch.cuda.current_stream(stream.device):
+        return
+    if all(s != stream for s in streams):
+        streams.append(stream)
+    for t in tensors:
+        t.record_stream(stream)
+
+
 class PbitError(RuntimeError):
     def __init__(self, code: int):
         super().__init__("%s (%d)" % (_lib.status_string(code), code))
@@ -47,12 +68,18 @@ class ListSorter:
     next: int32/uint32 tensor of n node indices (0xFFFFFFFF ends the list).
     keys: n unsigned (or, with ``signed=True``, two's-complement) integers, or
     floating-point values (float16/bfloat16/float32/float64), sorted by value.
+
+    A sorter holds one workspace and one result word, so sorts that may run at
+    the same time (queued on different streams) need a sorter each.  A sort
+    queued on a side stream keeps the workspace it used alive for that stream
+    when a later, larger sort replaces it.
     """
 
     def __init__(self, device="cuda"):
         self.device = torch.device(device)
         self._ws = None
         self._ws_bytes = 0
+        self._ws_streams = []
         self.result = torch.zeros(2, dtype=torch.int32, device=self.device)
 
     def workspace(self, n: int, M: int, K: int = 0) -> torch.Tensor:
@@ -60,6 +87,7 @@ class ListSorter:
         if need == 0:
             raise PbitError(_lib.EINVAL)
         if self._ws is None or self._ws_bytes < need:
+            _retire(self._ws, self._ws_streams)
             self._ws = None
             self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
             self._ws_bytes = need
@@ -83,6 +111,7 @@ class ListSorter:
         if result is None:
             result = self.result
         ws = self.workspace(n, M, K)
+        _note_stream(self._ws_streams, stream, result)
         flags = key_flags(keys, descending, signed)
         st = _lib.sort_list_async(head, next_in, next_out, keys, n, M, K, flags, result, ws,
                                   self._ws_bytes, stream)
@@ -117,6 +146,7 @@ class ListSorter:
         if int(nodes.numel()) * nodes.element_size() < n * stride:
             raise ValueError("nodes holds fewer than n records")
         ws = self.workspace(n, M, K)
+        _note_stream(self._ws_streams, stream, result)
         flags = ((_lib.DESCENDING if descending else 0) | (_lib.SIGNED if signed else 0)
                  | (_lib.FLOAT if floating else 0))
         st = _lib.sort_list_aos_async(head, nodes, stride, next_off, key_off, n, M, K, flags,
@@ -139,12 +169,14 @@ class ListsSorter:
 
     heads: int32/uint32 tensor [L]; offsets: int64 tensor [L+1] of slab bounds;
     next/keys: shared device arrays over all slabs.
+    Like ``ListSorter``: one sorter per stream for sorts that may overlap.
     """
 
     def __init__(self, device="cuda"):
         self.device = torch.device(device)
         self._ws = None
         self._ws_bytes = 0
+        self._ws_streams = []
         self.status = torch.zeros(1, dtype=torch.int32, device=self.device)
 
     def workspace(self, total: int, num_lists: int, M: int, K: int = 0) -> torch.Tensor:
@@ -152,6 +184,7 @@ class ListsSorter:
         if need == 0:
             raise PbitError(_lib.EINVAL)
         if self._ws is None or self._ws_bytes < need:
+            _retire(self._ws, self._ws_streams)
             self._ws = None
             self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
             self._ws_bytes = need
@@ -170,6 +203,7 @@ class ListsSorter:
         if status is None:
             status = self.status
         ws = self.workspace(total, L, M, K)
+        _note_stream(self._ws_streams, stream, new_heads, status)
         flags = key_flags(keys, descending, signed)
         st = _lib.sort_lists(heads, offsets, L, total, next_in, next_out, keys, M, K, flags,
                              new_heads, status, ws, self._ws_bytes, stream)

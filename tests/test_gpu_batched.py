@@ -179,3 +179,75 @@ def test_batched_rejects_malformed():
     bad_heads = heads.copy(); bad_heads[2] = 5
     st, _, _ = gpu_sort_lists(bad_heads, offs, nxt, keys, 8)
     assert st == -1
+
+
+def gpu_sort_lists_gather(heads_local, offsets, nexts, keys_list, K):
+    """The gather form: each list in arrays of its own, list-local indices.
+    Outputs start as all ones so that untouched entries can be seen."""
+    import torch
+    from paper_cs_0511020_amd import _lib
+    L = len(nexts)
+    M = keys_list[0].dtype.itemsize * 8
+    nt = [to_dev(x.astype(np.uint32), torch) for x in nexts]
+    kt = [to_dev(x, torch) for x in keys_list]
+    outs = [torch.full_like(x, -1) for x in nt]
+    ptrs = lambda ts: torch.tensor([t.data_ptr() for t in ts], dtype=torch.int64, device="cuda")
+    p_in, p_out, p_key = ptrs(nt), ptrs(outs), ptrs(kt)
+    ht = to_dev(np.asarray(heads_local, dtype=np.uint32), torch)
+    ot = torch.from_numpy(np.asarray(offsets, dtype=np.int64)).to("cuda")
+    total = int(sum(int(x.shape[0]) for x in nexts))
+    new_heads = torch.full((L,), -1, dtype=torch.int32, device="cuda")
+    status = torch.full((1,), 7, dtype=torch.int32, device="cuda")
+    wsb = _lib.lists_workspace_bytes(total, L, M, K)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    st = _lib.sort_lists_gather(ht, ot, L, total, p_in, p_out, p_key, M, K, 0, new_heads, status,
+                                ws, wsb)
+    assert st == 0
+    torch.cuda.synchronize()
+    return (int(status.item()), new_heads.cpu().numpy().view(np.uint32),
+            [o.cpu().numpy().view(np.uint32) for o in outs])
+
+
+def test_gather_form_and_its_rejections(oracle_mod):
+    """Gather-form batch against the oracle; then slab bounds that are not
+    monotone, that end below the node count, or a head outside its list:
+    status PBIT_EINVAL, no output or head written, nothing read out of
+    bounds."""
+    rng = inputs.rng_for(4601)
+    lengths = [300, 1, 0, 7000, 45]
+    nexts, heads, keys_list = [], [], []
+    for ln in lengths:
+        if ln:
+            nx, h, _ = inputs.random_list(ln, rng)
+        else:
+            nx, h = np.zeros(0, dtype=np.uint32), NIL
+        nexts.append(nx)
+        heads.append(h)
+        keys_list.append(rng.integers(0, 40, size=ln).astype(np.uint32))
+    offs = np.zeros(len(lengths) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum(lengths)
+    st, nh, outs = gpu_sort_lists_gather(heads, offs, nexts, keys_list, 8)
+    assert st == 0
+    for l, ln in enumerate(lengths):
+        if ln == 0:
+            assert nh[l] == NIL
+            continue
+        eh, enext = oracle_mod.sort_list(heads[l], nexts[l], keys_list[l], 32, 8)
+        assert nh[l] == eh and np.array_equal(outs[l], enext)
+
+    def rejected(h, o):
+        st, nh, outs = gpu_sort_lists_gather(h, o, nexts, keys_list, 8)
+        assert st == -1
+        assert np.all(nh == NIL)
+        assert all(np.all(x == NIL) for x in outs)
+
+    bad = offs.copy(); bad[2] = bad[4] + 3          # list 1 ends after list 3 starts
+    rejected(heads, bad)
+    bad = offs.copy(); bad[-1] -= 10                # last slab ends below the node count
+    rejected(heads, bad)
+    bad = offs.copy(); bad[1], bad[2] = bad[2], bad[1]  # decreasing bounds
+    rejected(heads, bad)
+    bad_heads = list(heads); bad_heads[3] = 7000    # head past its list's end
+    rejected(bad_heads, offs)
+    bad_heads = list(heads); bad_heads[2] = 0       # head given for an empty list
+    rejected(bad_heads, offs)
