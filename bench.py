@@ -67,6 +67,12 @@ def parse():
                     help="skip the graph-replay timing of the single-list sort")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the float-key sort and the backward-link repair timings")
+    ap.add_argument("--no-other-k", action="store_true",
+                    help="skip the same list sorted with the other pattern width (4 vs 8)")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the 2^26-node list with 64-bit keys and a 64-bit payload")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="threads of the all-core oracle baseline (0 = every core)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -97,6 +103,49 @@ def load_traffic(kernel: str, src_hash: str, config: dict):
 
 def percentile(sorted_vals, q):
     return sorted_vals[min(len(sorted_vals) - 1, int(round(q * (len(sorted_vals) - 1))))]
+
+
+def unsigned_order(torch, keys):
+    """int64 tensor whose signed order is the unsigned order of the stored keys
+    (keys arrive in signed storage of their width)."""
+    if keys.dtype == torch.uint8:
+        return keys.to(torch.int64)
+    if keys.dtype == torch.int16:
+        return keys.to(torch.int64) & 0xFFFF
+    if keys.dtype == torch.int32:
+        return keys.to(torch.int64) & 0xFFFFFFFF
+    if keys.dtype == torch.int64:
+        return keys ^ (-(1 << 63))
+    raise TypeError(keys.dtype)
+
+
+def relinked_ok(torch, head, nxt, keys, order):
+    """On the device, the properties that together fix the stable sort of a
+    list whose input order (node at each position) is `order`: exactly one
+    NIL; every node but the head has exactly one predecessor; along every link
+    the pair (key, input position) strictly increases, so the links form one
+    path from the head over all nodes, sorted by key with ties in input
+    order."""
+    n = int(nxt.numel())
+    if n == 0:
+        return head == 0xFFFFFFFF
+    if not 0 <= head < n:
+        return False
+    nil = nxt == -1
+    if int(nil.sum().item()) != 1:
+        return False
+    src = torch.nonzero(~nil).flatten()
+    tgt = nxt[src].to(torch.int64) & 0xFFFFFFFF
+    if not bool((tgt < n).all().item()):
+        return False
+    indeg = torch.bincount(tgt, minlength=n)
+    if not bool((indeg <= 1).all().item()) or int(indeg[head].item()) != 0:
+        return False
+    pos = torch.empty(n, dtype=torch.int64, device=nxt.device)
+    pos[order.to(torch.int64)] = torch.arange(n, device=nxt.device)
+    k = unsigned_order(torch, keys)
+    ks, kt = k[src], k[tgt]
+    return bool(((kt > ks) | ((kt == ks) & (pos[tgt] > pos[src]))).all().item())
 
 
 def stage_table(lib, pools, counts):
@@ -170,6 +219,49 @@ def run_plain(args, lib, torch, np, inputs, bytemodel, EventPool):
     got = next_out.cpu().numpy().view(np.uint32)
     exp_order = order[np.argsort(keys[order], kind="stable")]
     ok = (h0 == int(exp_order[0])) and bool(np.array_equal(got[exp_order[:-1]], exp_order[1:]))
+
+    # the other pattern width on the same input (K = 4 beside K = 8)
+    other = None
+    if K in (4, 8) and not args.no_other_k:
+        K2 = 12 - K
+        ws2_bytes = _lib.workspace_bytes(n, M, K2)
+        ws2 = torch.empty(ws2_bytes, dtype=torch.uint8, device=dev)
+        out2 = torch.empty_like(next_in)
+        res2 = torch.zeros(2, dtype=torch.int32, device=dev)
+        pools2 = [EventPool(max_ev) for _ in range(args.steps)]
+
+        def run2(pool):
+            st = lib.pbit_sort_list_profiled(
+                head, next_in.data_ptr(), out2.data_ptr(), keys_d.data_ptr(), n, M, K2, 0,
+                res2.data_ptr(), ws2.data_ptr(), ws2_bytes, sh, pool.ptr(), pool.ids_ptr(),
+                max_ev, ctypes.byref(rec))
+            if st != 0:
+                raise RuntimeError("sort failed: " + _lib.status_string(st))
+            return rec.value
+
+        for _ in range(2):
+            run2(warm)
+        torch.cuda.synchronize()
+        cnt2 = [run2(pools2[k]) for k in range(args.steps)]
+        torch.cuda.synchronize()
+        st2, ln2, lat2 = stage_table(lib, pools2, cnt2)
+        h2 = int(res2[0].item()) & 0xFFFFFFFF
+        g2 = out2.cpu().numpy().view(np.uint32)
+        ok2 = h2 == int(exp_order[0]) and bool(np.array_equal(g2[exp_order[:-1]], exp_order[1:]))
+        ex2 = ln2.get("digit_pass", M // K2)
+        pass2 = st2.get("digit_pass", 0.0) / max(ex2, 1)
+        w2 = M // 8
+        pb2 = (bytemodel.kernel_bytes_per_node("digit_pass", w2) * (ex2 - 1)
+               + bytemodel.kernel_bytes_per_node("digit_pass", w2, last_pass=True)) / ex2
+        other = {"K": K2, "p50_ms": round(statistics.median(lat2), 4),
+                 "Mnodes_s_at_p50": round(n / (statistics.median(lat2) * 1e-3) / 1e6, 1),
+                 "digit_passes": ex2, "digit_pass_ms": round(pass2, 5),
+                 "digit_pass_frac": round(pb2 * n / (pass2 * 1e-3) / 1e9
+                                          / bytemodel.MI355X_HBM_PEAK_GBS, 4) if pass2 else None,
+                 "correct": ok2}
+        for p_ in pools2:
+            p_.close()
+        del ws2, out2
 
     # the same sort captured once in a HIP graph and replayed (no per-kernel
     # launch work on the host); reported beside the eager rate
@@ -250,7 +342,7 @@ def run_plain(args, lib, torch, np, inputs, bytemodel, EventPool):
         "value": n / (wall_ms * 1e-3) / 1e6, "wall_ms": wall_ms, "p50": p50, "p99": p99,
         "roofline": roofline, "stage_ms": stage_ms, "launches": launches, "correct": ok,
         "path_bpn": path_bpn, "path_frac": path_frac, "Keff": Keff, "src_hash": src_hash,
-        "graph_ms": graph_ms, "cold": cold,
+        "graph_ms": graph_ms, "cold": cold, "other_k": other,
     }
 
 
@@ -395,6 +487,64 @@ def run_extras(args, lib, torch, np, inputs, bytemodel):
     }
 
 
+def run_c3(args, lib, torch, np, bytemodel):
+    """One list of 2^26 nodes with uniform 64-bit keys and a 64-bit payload per
+    node (nodes never move, so the payload needs no handling), random layout,
+    K = 8 and K = 4; inputs built on the device from a seeded generator;
+    checked on the device by the properties that fix the stable sort."""
+    from paper_cs_0511020_amd import _lib
+    dev = torch.device("cuda:0")
+    n, M = 1 << 26, 64
+    g = torch.Generator(device=dev)
+    g.manual_seed(3001)
+    order = torch.randperm(n, generator=g, device=dev, dtype=torch.int64)
+    nxt = torch.full((n,), -1, dtype=torch.int32, device=dev)
+    nxt[order[:-1]] = order[1:].to(torch.int32)
+    head = int(order[0].item())
+    hi = torch.randint(-(1 << 31), 1 << 31, (n,), generator=g, device=dev, dtype=torch.int64)
+    lo = torch.randint(0, 1 << 32, (n,), generator=g, device=dev, dtype=torch.int64)
+    keys = (hi << 32) | lo
+    del hi, lo
+    payload = torch.randint(-(1 << 62), 1 << 62, (n,), generator=g, device=dev,
+                            dtype=torch.int64)
+    out = torch.empty_like(nxt)
+    res = torch.zeros(2, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    steps = max(3, args.steps // 4)
+    rows = {}
+    for K in (8, 4):
+        wsb = _lib.workspace_bytes(n, M, K)
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+
+        def sort():
+            st = _lib.sort_list_async(head, nxt, out, keys, n, M, K, 0, res, ws, wsb, stream)
+            if st != 0:
+                raise RuntimeError("u64 sort failed: " + _lib.status_string(st))
+
+        sort()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
+        for k in range(steps):
+            ev[2 * k].record(stream)
+            sort()
+            ev[2 * k + 1].record(stream)
+        torch.cuda.synchronize()
+        ms = statistics.median(ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(steps))
+        h = int(res[0].item()) & 0xFFFFFFFF
+        ok = int(res[1].item()) == 0 and relinked_ok(torch, h, out, keys, order)
+        passes = M // K
+        bpn = bytemodel.path_bytes_per_node(8, passes)
+        rows["K%d" % K] = {"ms": round(ms, 4), "Mnodes_per_s": round(n / (ms * 1e-3) / 1e6, 1),
+                           "path_frac": round(bpn * n / (ms * 1e-3) / 1e9
+                                              / bytemodel.MI355X_HBM_PEAK_GBS, 4),
+                           "correct": ok}
+        del ws
+        torch.cuda.empty_cache()
+    del order, nxt, keys, payload, out
+    torch.cuda.empty_cache()
+    return dict(workload="single list n=2^26, uint64 keys uniform, a uint64 payload per node, "
+                         "random-permutation layout", **rows)
+
+
 def run_batched(args, lib, torch, np, inputs, EventPool):
     """20 000 lists, log-uniform lengths in [16, 2^hi]: one batched call vs
     one single-list call per list, same inputs, same stream."""
@@ -479,9 +629,31 @@ def run_batched(args, lib, torch, np, inputs, EventPool):
     except Exception as exc:  # graph capture is optional for the measurement
         graph_ok = "unavailable: %s" % exc
 
+    # sampled lists against the oracle (the longest and seven seeded picks)
+    import oracle
+    offs_h = d["offsets_host"]
+    heads_h = d["heads_host"]
+    picks = [int(np.argmax(lengths))] + [int(x) for x in inputs.rng_for(4003).choice(L, 7, replace=False)]
+    nh_h = new_heads.cpu().numpy().view(np.uint32)
+    oracle_ok = int(status.item()) == 0
+
+    def local(x, lo):
+        x = x.astype(np.int64)
+        return np.where(x == 0xFFFFFFFF, 0xFFFFFFFF, x - lo).astype(np.uint32)
+
+    for l in picks:
+        lo, hi_ = int(offs_h[l]), int(offs_h[l + 1])
+        eh, en = oracle.sort_list(int(heads_h[l]) - lo,
+                                  local(d["next"][lo:hi_].cpu().numpy().view(np.uint32), lo),
+                                  d["keys"][lo:hi_].cpu().numpy().view(np.uint32), 32, 8)
+        oracle_ok = oracle_ok and int(nh_h[l]) - lo == eh and bool(np.array_equal(
+            local(next_out[lo:hi_].cpu().numpy().view(np.uint32), lo), en))
+
     out = {
         "workload": "20000 lists, lengths log-uniform in [16, 2^%d], %d nodes, uint32 keys, "
                     "random layout per slab, K=8" % (hi, total),
+        "oracle_sampled_lists": len(picks),
+        "oracle_equal": oracle_ok,
         "lists": L, "nodes": total,
         "batched_ms": round(wall_ms, 3),
         "batched_Mnodes_s": round(total / (wall_ms * 1e-3) / 1e6, 1),
@@ -548,7 +720,12 @@ def run_served(args, torch, np, inputs):
                                             make_requests_device)
     full = args.served == "full"
     count, hi = (2000, 24) if full else (300, 20)
-    reqs = make_requests_device(count, seed=5001, lo_log2=10, hi_log2=hi)
+    reqs = make_requests_device(count, seed=5001, lo_log2=10, hi_log2=hi, keep_order=True)
+
+    def all_relinked():
+        """Every request's result has the properties of its stable sort."""
+        return all(r.status == 0 and relinked_ok(torch, r.new_head, r.out, r.keys, r.order)
+                   for r in reqs)
     torch.cuda.synchronize()
     free = torch.cuda.mem_get_info()[0]
     budget = int(free * 0.6)
@@ -570,7 +747,22 @@ def run_served(args, torch, np, inputs):
     reset(np.zeros(count))
     sat = SortServer(GpuExecutor(streams=2), slots=64, budget_bytes=budget).run(reqs)
     X = sat.throughput_mnodes_s * 1e6
-    ok = all(r.status == 0 for r in reqs)
+    checked = 1
+    ok = all_relinked()
+    # a few requests of every key width against the oracle
+    import oracle
+    dt = {8: np.uint8, 16: np.uint16, 32: np.uint32, 64: np.uint64}
+    srng = inputs.rng_for(5003)
+    sample = []
+    for M in (8, 16, 32, 64):
+        cand = [r for r in reqs if r.M == M and r.n <= (1 << 18)]
+        sample += [cand[int(i)] for i in srng.choice(len(cand), min(2, len(cand)),
+                                                      replace=False)]
+    for r in sample:
+        eh, en = oracle.sort_list(r.head, r.next.cpu().numpy().view(np.uint32),
+                                  r.keys.cpu().numpy().view(dt[r.M]), r.M, 4 if r.M == 8 else 8)
+        ok = ok and eh == r.new_head and bool(
+            np.array_equal(r.out.cpu().numpy().view(np.uint32), en))
     loads = {}
     for frac in ((0.5, 0.7, 0.9) if full else (0.7,)):
         rng = inputs.rng_for(5002)
@@ -578,10 +770,11 @@ def run_served(args, torch, np, inputs):
         arrivals = np.cumsum(rng.exponential(1.0 / lam, size=count))
         reset(arrivals)
         opened = SortServer(GpuExecutor(streams=2), slots=64, budget_bytes=budget).run(reqs)
-        ok = ok and all(r.status == 0 for r in reqs)
+        ok = ok and all_relinked()
         reset(arrivals)
         fifo = SortServer(PlainExecutor(), slots=1, budget_bytes=budget).run(reqs)
-        ok = ok and all(r.status == 0 for r in reqs)
+        ok = ok and all_relinked()
+        checked += 2
         loads[frac] = (summary(opened), summary(fifo))
     opened_s, fifo_s = loads[0.7]
     out = {
@@ -596,6 +789,11 @@ def run_served(args, torch, np, inputs):
         "by_load": {"%.1f" % f: {"offered_mnodes_s": round(f * X / 1e6, 1), "batched": b,
                                  "fifo_plain": p} for f, (b, p) in loads.items()},
         "all_ok": ok,
+        "checks": "after each of the %d runs every request's result is checked on the device "
+                  "for the properties of its stable sort (one path from the head over all "
+                  "nodes, (key, input position) increasing along every link); %d requests "
+                  "(two per key width, up to 2^18 nodes) are compared with the oracle"
+                  % (checked, len(sample)),
     }
     del reqs
     torch.cuda.empty_cache()
@@ -628,6 +826,10 @@ def main():
         extras = run_extras(args, lib, torch, np, inputs, bytemodel)
         torch.cuda.empty_cache()
 
+    c3 = None
+    if not args.no_c3:
+        c3 = run_c3(args, lib, torch, np, bytemodel)
+
     batched = None
     if args.batched != "none":
         batched = run_batched(args, lib, torch, np, inputs, EventPool)
@@ -651,15 +853,52 @@ def main():
         cnxt, chead, _ = inputs.random_list(cn, crng)
         ckeys = inputs.keys_by_distribution(args.dist, cn, crng)
         oracle.build(force=False)
-        tc0 = time.perf_counter()
         if args.M == 64:
             ckeys = inputs.uniform_keys(cn, 64, crng)
-        oracle.sort_list(chead, cnxt, ckeys, args.M, r["Keff"])
+        tc0 = time.perf_counter()
+        ch, cout = oracle.sort_list(chead, cnxt, ckeys, args.M, r["Keff"])
         tc1 = time.perf_counter()
+        # (ii) the same oracle with the groups below its top levels on every core
+        threads = args.cpu_threads or (os.cpu_count() or 1)
+        tp0 = time.perf_counter()
+        ph, pout = oracle.sort_list_threads(chead, cnxt, ckeys, args.M, r["Keff"],
+                                            threads=threads)
+        tp1 = time.perf_counter()
+        # (iii) context: walk the list, stable-sort its keys (numpy), relink
+        tw0 = time.perf_counter()
+        corder = oracle.list_order(chead, cnxt)
+        sorted_nodes = corder[np.argsort(ckeys[corder], kind="stable")]
+        wout = np.empty_like(cnxt)
+        wout[sorted_nodes[:-1]] = sorted_nodes[1:]
+        wout[sorted_nodes[-1]] = 0xFFFFFFFF
+        tw1 = time.perf_counter()
+        agree = (ch == ph == int(sorted_nodes[0]) and bool(np.array_equal(cout, pout))
+                 and bool(np.array_equal(cout, wout)))
+        cpu_model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        cpu_model = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
         cpu = {"value": round(cn / (tc1 - tc0) / 1e6, 3), "unit": "Mnodes/s", "cores": 1,
                "kind": "oracle",
                "sample": "one sort of a %d-node list, same key distribution and layout recipe, "
-                         "K=%d, single-threaded C oracle, %.1f s" % (cn, r["Keff"], tc1 - tc0)}
+                         "K=%d, single-threaded C oracle, %.1f s" % (cn, r["Keff"], tc1 - tc0),
+               "nproc": os.cpu_count(), "cpu_model": cpu_model,
+               "all_cores": {"value": round(cn / (tp1 - tp0) / 1e6, 3), "unit": "Mnodes/s",
+                             "cores": threads, "kind": "oracle",
+                             "sample": "the same list; top pattern levels split on one thread, "
+                                       "the groups below sorted on %d threads, %.1f s"
+                                       % (threads, tp1 - tp0)},
+               "walk_stable_sort_relink": {"value": round(cn / (tw1 - tw0) / 1e6, 3),
+                                           "unit": "Mnodes/s", "cores": 1, "kind": "context",
+                                           "sample": "the same list walked, its keys stably "
+                                                     "sorted by numpy, relinked, %.1f s"
+                                                     % (tw1 - tw0)},
+               "variants_agree": agree}
 
     out = {
         "metric": METRIC,
@@ -679,6 +918,11 @@ def main():
                                % (args.n, args.M, args.dist if args.M == 32 else "uniform",
                                   r["Keff"]),
                    "n": args.n, "M": args.M, "K": r["Keff"], "dist": args.dist, "mode": "plain"},
+        "timing": "value and ms_per_step: warm, %d back-to-back sorts of the same resident "
+                  "input (out of place) after %d warm-up sorts, wall clock around them; "
+                  "latency_ms from HIP events per sort; cold_latency_ms: each sort after a "
+                  "1 GiB write that flushes L2 and the last-level cache" % (args.steps,
+                                                                            args.warmup),
         "roofline": r["roofline"],
         "cpu_baseline": cpu,
         "latency_ms": {"p50": round(r["p50"], 4), "p99": round(r["p99"], 4)},
@@ -689,6 +933,8 @@ def main():
         "stages_ms": {k: round(v, 4) for k, v in sorted(r["stage_ms"].items(), key=lambda x: -x[1])},
         "stage_launches": r["launches"],
         "correct": r["correct"],
+        "other_k": r["other_k"],
+        "c3_u64_payload": c3,
         "extras": extras,
         "batched": batched,
         "served": served,

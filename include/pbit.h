@@ -32,7 +32,7 @@
  * Errors are negative return values:
  *   PBIT_EINVAL     bad argument found on the host (no device work queued):
  *                   M not in {8,16,32,64}, K not in {0,1,2,4,8} or not
- *                   dividing M, n >= 2^30, head >= n, null pointer,
+ *                   dividing M, n >= 2^32 - 1, head >= n, null pointer,
  *                   an unknown flag bit or PBIT_SIGNED with PBIT_FLOAT,
  *                   workspace too small (see PBIT_ENOMEM);
  *   PBIT_EMALFORMED found on the device: an index >= n, a cycle, or a list
@@ -52,7 +52,9 @@ extern "C" {
 #endif
 
 #define PBIT_NIL 0xFFFFFFFFu
-#define PBIT_MAX_NODES ((1u << 30) - 1u)
+/* Largest list: node indices are uint32 with 0xFFFFFFFF as NIL (Sec. 3
+ * assumes 32-bit pointers). */
+#define PBIT_MAX_NODES 0xFFFFFFFEu
 
 enum {
     PBIT_OK = 0,
@@ -73,8 +75,9 @@ enum {
  * Bytes of device workspace needed to sort a list of n nodes with M-bit keys
  * and K-bit patterns (K = 0: the library picks).  Returns 0 for arguments
  * pbit_sort_list_async would reject.  The workspace is O(n): for 32-bit
- * keys about 94 bytes per node up to 2^26 nodes and about 62 beyond (the
- * per-chain slots of the ranking shrink); about 174 for 64-bit keys.
+ * keys about 94 bytes per node up to 2^26 nodes, about 62 up to 2^31 and
+ * about 46 beyond (the per-chain slots of the ranking shrink); about 174 for
+ * 64-bit keys up to 2^26 nodes.
  */
 size_t pbit_workspace_bytes(uint64_t n, uint32_t M, uint32_t K);
 

@@ -39,8 +39,8 @@ def build(force: bool = True) -> str:
     ):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC",
-             _SRC, "-o", tmp]
+            ["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-Wall", "-Wextra", "-shared",
+             "-fPIC", "-pthread", _SRC, "-o", tmp]
         )
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -57,6 +57,10 @@ def _load():
             ctypes.c_uint32, u32p, ctypes.c_void_p, ctypes.c_uint64,
             ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
             ctypes.POINTER(ctypes.c_uint64)]
+        lib.pbit_oracle_sort_threads.restype = ctypes.c_int64
+        lib.pbit_oracle_sort_threads.argtypes = [
+            ctypes.c_uint32, u32p, ctypes.c_void_p, ctypes.c_uint64,
+            ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32]
         lib.pbit_oracle_sort_lists.restype = ctypes.c_int
         lib.pbit_oracle_sort_lists.argtypes = [
             u32p, ctypes.POINTER(ctypes.c_uint64), ctypes.c_uint32, u32p,
@@ -103,6 +107,21 @@ def sort_list(head: int, next_: np.ndarray, keys: np.ndarray, M: int, K: int,
                              nxt.shape[0], M, K, flags, cnt)
     if counters:
         return int(h), nxt, tuple(int(c) for c in cnt)
+    return int(h), nxt
+
+
+def sort_list_threads(head: int, next_: np.ndarray, keys: np.ndarray, M: int, K: int,
+                      flags: int = 0, threads: int = 0):
+    """The same sort with the groups below the top levels sorted on host
+    threads (0 = every online core); unsigned keys, ascending or descending.
+    Returns (new_head_or_status, relinked_next)."""
+    lib = _load()
+    nxt = np.array(next_, dtype=np.uint32, copy=True)
+    keys = _check_keys(keys, M)
+    if keys.shape[0] != nxt.shape[0]:
+        raise ValueError("keys and next differ in length")
+    h = lib.pbit_oracle_sort_threads(int(head) & 0xFFFFFFFF, _u32p(nxt), keys.ctypes.data,
+                                     nxt.shape[0], M, K, flags, int(threads))
     return int(h), nxt
 
 

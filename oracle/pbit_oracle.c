@@ -45,9 +45,11 @@
  * Extra memory is O(Omega * M/K) group roots (Sec. 3, the bound T), never
  * proportional to n.
  */
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <unistd.h>
 
 #define ORACLE_NIL 0xFFFFFFFFu
 
@@ -361,4 +363,168 @@ int64_t pbit_oracle_repair_prev(uint32_t head, const uint32_t *next, uint64_t n,
         behind = i;
     }
     return (int64_t)steps;
+}
+
+/*
+ * The same sort on several host threads (a CPU baseline, not a pin).  The top
+ * levels of the recursion run as in pbit_oracle_sort: the list is split into
+ * first-in-first-out groups on the top pattern, and, while fewer than 256
+ * groups exist and bits remain, each group again on the next pattern.  The
+ * groups are independent sub-lists (Sec. 3), so each is sorted by the
+ * recursion of Sec. 5 on its own thread, which then walks its result to the
+ * end (the walk of the merge of Sec. 5.1) so that the groups can be joined in
+ * pattern order without a second walk.  Unsigned keys only; flags 0 or
+ * ORACLE_FLAG_DESCENDING.  threads = 0 uses every online core.  Returns the
+ * new head or a negative status.
+ */
+typedef struct {
+    uint32_t head, tail;  /* sorted sub-list, or NIL */
+    uint32_t m;           /* bits still to split below */
+} oracle_task;
+
+typedef struct {
+    pbit_oracle_ctx proto;
+    oracle_task *tasks;
+    uint32_t n_tasks;
+    uint32_t next_task;
+    pthread_mutex_t mu;
+    int failed;
+} oracle_pool;
+
+static void *oracle_worker(void *arg)
+{
+    oracle_pool *pool = (oracle_pool *)arg;
+    pbit_oracle_ctx c = pool->proto;
+    c.roots = (uint32_t *)malloc((size_t)(c.width / c.K) * 2u * c.omega * sizeof(uint32_t));
+    if (!c.roots) {
+        pthread_mutex_lock(&pool->mu);
+        pool->failed = 1;
+        pthread_mutex_unlock(&pool->mu);
+        return NULL;
+    }
+    for (;;) {
+        pthread_mutex_lock(&pool->mu);
+        uint32_t t = pool->next_task++;
+        pthread_mutex_unlock(&pool->mu);
+        if (t >= pool->n_tasks)
+            break;
+        oracle_task *tk = &pool->tasks[t];
+        if (tk->head == ORACLE_NIL)
+            continue;
+        uint32_t h = tk->m > 0 ? oracle_pbit(&c, tk->head, tk->m, ORACLE_NIL) : tk->head;
+        uint32_t last = h;
+        while (c.next[last] != ORACLE_NIL)
+            last = c.next[last];
+        tk->head = h;
+        tk->tail = last;
+    }
+    free(c.roots);
+    return NULL;
+}
+
+/* One split level over every task: task i becomes omega tasks in pattern
+ * order, each a first-in-first-out group. */
+static oracle_task *oracle_split_tasks(const pbit_oracle_ctx *c, const oracle_task *in,
+                                       uint32_t n_in)
+{
+    oracle_task *out = (oracle_task *)malloc((size_t)n_in * c->omega * sizeof(oracle_task));
+    if (!out)
+        return NULL;
+    for (uint32_t t = 0; t < n_in; t++) {
+        oracle_task *g = out + (size_t)t * c->omega;
+        uint32_t m = in[t].m - c->K;
+        for (uint32_t d = 0; d < c->omega; d++) {
+            g[d].head = g[d].tail = ORACLE_NIL;
+            g[d].m = m;
+        }
+        for (uint32_t i = in[t].head; i != ORACLE_NIL;) {
+            uint32_t following = c->next[i];
+            uint32_t d = (uint32_t)((oracle_key(c, i) >> m) & (uint64_t)(c->omega - 1u));
+            c->next[i] = ORACLE_NIL;
+            if (g[d].head == ORACLE_NIL)
+                g[d].head = i;
+            else
+                c->next[g[d].tail] = i;
+            g[d].tail = i;
+            i = following;
+        }
+    }
+    return out;
+}
+
+int64_t pbit_oracle_sort_threads(uint32_t head, uint32_t *next, const void *keys, uint64_t n,
+                                 uint32_t M, uint32_t K, uint32_t flags, uint32_t threads)
+{
+    if (!oracle_valid_shape(M, K) || (flags & ~(uint32_t)ORACLE_FLAG_DESCENDING))
+        return ORACLE_EINVAL;
+    if (n >= (uint64_t)ORACLE_NIL)
+        return ORACLE_EINVAL;
+    if (n == 0 || head == ORACLE_NIL)
+        return (n == 0 && head == ORACLE_NIL) ? (int64_t)ORACLE_NIL : ORACLE_EINVAL;
+    if (!next || !keys || head >= n)
+        return ORACLE_EINVAL;
+    int st = oracle_walk_check(head, next, n, 0, (uint32_t)n);
+    if (st != ORACLE_OK)
+        return st;
+    if (threads == 0) {
+        long p = sysconf(_SC_NPROCESSORS_ONLN);
+        threads = p > 0 ? (uint32_t)p : 1u;
+    }
+    oracle_pool pool;
+    memset(&pool, 0, sizeof pool);
+    pool.proto.next = next;
+    pool.proto.keys = keys;
+    pool.proto.width = M;
+    pool.proto.K = K;
+    pool.proto.omega = 1u << K;
+    pool.proto.descending = (flags & ORACLE_FLAG_DESCENDING) != 0;
+
+    oracle_task *tasks = (oracle_task *)malloc(sizeof(oracle_task));
+    if (!tasks)
+        return ORACLE_ENOMEM;
+    tasks[0].head = head;
+    tasks[0].m = M;
+    uint32_t n_tasks = 1;
+    do {
+        oracle_task *split = oracle_split_tasks(&pool.proto, tasks, n_tasks);
+        free(tasks);
+        if (!split)
+            return ORACLE_ENOMEM;
+        tasks = split;
+        n_tasks *= pool.proto.omega;
+    } while (n_tasks < 256u && tasks[0].m > 0);
+
+    pool.tasks = tasks;
+    pool.n_tasks = n_tasks;
+    pthread_mutex_init(&pool.mu, NULL);
+    pthread_t *tid = (pthread_t *)malloc((size_t)threads * sizeof(pthread_t));
+    uint32_t started = 0;
+    if (tid)
+        for (; started < threads; started++)
+            if (pthread_create(&tid[started], NULL, oracle_worker, &pool) != 0)
+                break;
+    if (started == 0)
+        oracle_worker(&pool);
+    for (uint32_t t = 0; t < started; t++)
+        pthread_join(tid[t], NULL);
+    free(tid);
+    pthread_mutex_destroy(&pool.mu);
+    if (pool.failed) {
+        free(tasks);
+        return ORACLE_ENOMEM;
+    }
+    /* join the sorted groups in pattern order (Sec. 6 for the direction) */
+    uint32_t first = ORACLE_NIL, last = ORACLE_NIL;
+    for (uint32_t s = 0; s < n_tasks; s++) {
+        const oracle_task *tk = &tasks[pool.proto.descending ? n_tasks - 1u - s : s];
+        if (tk->head == ORACLE_NIL)
+            continue;
+        if (first == ORACLE_NIL)
+            first = tk->head;
+        else
+            next[last] = tk->head;
+        last = tk->tail;
+    }
+    free(tasks);
+    return (int64_t)first;
 }

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpbit.so")
 
 NIL = 0xFFFFFFFF
-MAX_NODES = (1 << 30) - 1
+MAX_NODES = (1 << 32) - 2
 OK, EINVAL, EMALFORMED, ENOMEM, EHIP = 0, -1, -2, -3, -4
 ASCENDING, DESCENDING, SIGNED, FLOAT = 0, 1, 2, 4
 

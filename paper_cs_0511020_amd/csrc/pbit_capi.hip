@@ -84,6 +84,7 @@ static bool plan_common(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, uint
     if (P->passes > (uint32_t)kMaxPasses)
         return false;
     P->flags = flags;
+    P->look64 = lw_bytes == 8;
     P->spin_limit = g_spin_limit.load(std::memory_order_relaxed);
     P->key_bytes = M / 8;
     P->tile = pass_tile(P->key_bytes, P->RB);
@@ -140,8 +141,11 @@ bool make_plan(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, Plan* P)
     }
     const uint32_t reg = reg_entries(M / 8);
     const uint32_t cap = level0_cap(n, reg);
+    // a look-back word holds a 30-bit count next to its 2 flag bits; from
+    // 2^30 nodes on the words are 64 bits wide
+    const size_t lw_bytes = n >= (1ull << 30) ? 8 : 4;
     size_t off = 0;
-    if (!plan_common(n, M, K, flags, 0, 4, 1 + ceil_div(n, 1ull << kLog0), cap, P, off))
+    if (!plan_common(n, M, K, flags, 0, lw_bytes, 1 + ceil_div(n, 1ull << kLog0), cap, P, off))
         return false;
     int k = 1;
     uint64_t m = P->lv[0].n_static;

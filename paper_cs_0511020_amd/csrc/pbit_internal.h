@@ -100,6 +100,7 @@ struct Plan {
     uint32_t tile, tiles;
     uint32_t key_passes;  // passes on key patterns; the rest split on list ids
     uint32_t spin_limit;  // look-back sleeps on one predecessor before the fallback
+    uint32_t look64;      // 64-bit look-back words (counts of 2^30 and more)
     uint32_t num_lists;   // many-list sorts
     uint32_t log_block;   // many-list sorts: node block size of the list table
     int levels;           // walk levels; the base ranks level `levels`

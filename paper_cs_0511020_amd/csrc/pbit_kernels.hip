@@ -463,11 +463,20 @@ static hipError_t enqueue_after_pack(const Plan& P, uint32_t head, char* out_bas
     }
     if (e != hipSuccess)
         return e;
-    switch (P.key_bytes) {
-    case 1: e = launch_passes<uint8_t, uint32_t>(P, ws, s, prof, LidMap{}, true); break;
-    case 2: e = launch_passes<uint16_t, uint32_t>(P, ws, s, prof, LidMap{}, true); break;
-    case 4: e = launch_passes<uint32_t, uint32_t>(P, ws, s, prof, LidMap{}, true); break;
-    default: e = launch_passes<uint64_t, uint32_t>(P, ws, s, prof, LidMap{}, true); break;
+    if (P.look64) {
+        switch (P.key_bytes) {
+        case 1: e = launch_passes<uint8_t, uint64_t>(P, ws, s, prof, LidMap{}, true); break;
+        case 2: e = launch_passes<uint16_t, uint64_t>(P, ws, s, prof, LidMap{}, true); break;
+        case 4: e = launch_passes<uint32_t, uint64_t>(P, ws, s, prof, LidMap{}, true); break;
+        default: e = launch_passes<uint64_t, uint64_t>(P, ws, s, prof, LidMap{}, true); break;
+        }
+    } else {
+        switch (P.key_bytes) {
+        case 1: e = launch_passes<uint8_t, uint32_t>(P, ws, s, prof, LidMap{}, true); break;
+        case 2: e = launch_passes<uint16_t, uint32_t>(P, ws, s, prof, LidMap{}, true); break;
+        case 4: e = launch_passes<uint32_t, uint32_t>(P, ws, s, prof, LidMap{}, true); break;
+        default: e = launch_passes<uint64_t, uint32_t>(P, ws, s, prof, LidMap{}, true); break;
+        }
     }
     if (e != hipSuccess)
         return e;

@@ -48,6 +48,7 @@ class Request:
     done: float = -1.0
     batch: int = -1
     share: int = 0            # workspace bytes reserved while admitted
+    order: Any = None         # optional: the input list order (node at each position)
 
     @property
     def latency(self) -> float:
@@ -307,11 +308,12 @@ class SortServer:
 
 def make_requests_device(count: int, seed: int, lo_log2: float = 10, hi_log2: float = 24,
                          widths=(8, 16, 32, 64), rate_nodes_s: float | None = None,
-                         device="cuda"):
+                         device="cuda", keep_order: bool = False):
     """Seeded request mix kept in device memory: length log-uniform in
     [2^lo, 2^hi], key width uniform over `widths`, uniform keys, random list
     layout; Poisson arrivals at `rate_nodes_s` offered nodes per second (all
-    at time 0 when None)."""
+    at time 0 when None).  With keep_order each request also keeps its input
+    list order (int32 device tensor), for checking results."""
     import torch
 
     from . import inputs
@@ -347,5 +349,6 @@ def make_requests_device(count: int, seed: int, lo_log2: float = 10, hi_log2: fl
             keys = (hi << 32) | lo
         reqs.append(Request(rid=i, arrival=float(arrivals[i]), n=n, M=M,
                             head=int(perm[0].item()), next=nxt, keys=keys,
-                            out=torch.empty_like(nxt)))
+                            out=torch.empty_like(nxt),
+                            order=perm.to(torch.int32) if keep_order else None))
     return reqs

@@ -54,7 +54,12 @@ def test_workspace_bytes_shapes(lib):
     assert _lib.workspace_bytes(1000, 32, 3) == 0
     assert _lib.workspace_bytes(1000, 32, 16) == 0
     assert _lib.workspace_bytes(1000, 8, 16) == 0
-    assert _lib.workspace_bytes(1 << 30, 32, 4) == 0
+    assert _lib.workspace_bytes((1 << 32) - 1, 32, 4) == 0
+    # from 2^30 nodes on the look-back words are 8 bytes: the look-back array
+    # grows by (passes x tiles x radix x 4) bytes at that step
+    below, above = _lib.workspace_bytes((1 << 30) - 1, 8, 4), _lib.workspace_bytes(1 << 30, 8, 4)
+    assert above - below >= 2 * ((1 << 30) // 6144) * 16 * 4
+    assert _lib.workspace_bytes((1 << 32) - 2, 8, 8) > 0
     # the workspace grows linearly with n
     a, b = _lib.workspace_bytes(1 << 20, 32, 8), _lib.workspace_bytes(1 << 21, 32, 8)
     assert 1.8 < b / a < 2.2
@@ -94,7 +99,7 @@ def test_host_argument_checks(lib):
     assert _call(lib, ws=0) == E
     assert _call(lib, keys=0x1002, M=32) == E     # misaligned keys
     assert _call(lib, ws=0x100010) == E           # misaligned workspace
-    assert _call(lib, n=1 << 30) == E
+    assert _call(lib, n=(1 << 32) - 1) == E
     assert _call(lib, ws_bytes=16) == _lib.ENOMEM
     # the synchronous form checks the same way before touching a device
     assert lib.pbit_sort_list(0, 0x1000, 0x1000, 8, 12, 4) == E

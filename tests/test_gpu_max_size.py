@@ -1,6 +1,8 @@
-"""The largest single list the boundary accepts, n = 2^30 - 1, with 8-bit keys
-(so many ties).  The oracle cannot run at this size, so the result is checked
-on the device by properties that together fix the stable sort:
+"""Single lists beyond the sizes the oracle can sort in a test, with 8-bit
+keys (so many ties): n = 2^30 - 1, the largest list whose digit passes chain
+tiles with 32-bit look-back words (2 flag bits and a 30-bit count), and
+n = 2^30 + 2^20, which takes the 64-bit words.  The result is checked on the
+device by properties that together fix the stable sort:
 
 * every node but one (the head) has exactly one predecessor and exactly one
   node links to NIL;
@@ -15,7 +17,6 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
-N_MAX = (1 << 30) - 1
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -25,15 +26,14 @@ def _gpu():
         pytest.skip("no GPU")
 
 
-def test_max_size_u8_keys():
+@pytest.mark.parametrize("n", [(1 << 30) - 1, (1 << 30) + (1 << 20)])
+def test_largest_lists_u8_keys(n):
     import torch
-    from paper_cs_0511020_amd import _lib
     from paper_cs_0511020_amd.sorter import ListSorter
-    print("max size n=%d u8 keys" % N_MAX, flush=True)
+    print("large list n=%d u8 keys" % n, flush=True)
     dev = torch.device("cuda")
     g = torch.Generator(device=dev)
-    g.manual_seed(3030)
-    n = N_MAX
+    g.manual_seed(3030 + n)
     order = torch.randperm(n, generator=g, device=dev, dtype=torch.int64)  # list order
     nxt = torch.full((n,), -1, dtype=torch.int32, device=dev)
     nxt[order[:-1]] = order[1:].to(torch.int32)

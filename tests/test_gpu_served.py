@@ -57,3 +57,43 @@ def test_fifo_baseline_executor():
     for r in reqs:
         h, out = _alone(torch, r)
         assert r.new_head == h and torch.equal(r.out, out)
+
+
+def test_served_full_size_mix(oracle_mod):
+    """Requests of 2^10..2^24 nodes over all four key widths, all arriving at
+    once, so the first ticks batch requests of very different sizes through
+    the gather form.  Every request must equal the single-list sort of it
+    alone; per key width the largest request up to 2^23 nodes is checked
+    against the oracle."""
+    import torch
+    from paper_cs_0511020_amd.serve import GpuExecutor, SortServer, make_requests_device
+    reqs = make_requests_device(40, seed=5003, lo_log2=10, hi_log2=24)
+    print("full-size mix: %d requests, %d nodes, largest %d" % (
+        len(reqs), sum(r.n for r in reqs), max(r.n for r in reqs)), flush=True)
+    server = SortServer(GpuExecutor(streams=2), slots=16, budget_bytes=96 << 30)
+    st = server.run(reqs)
+    torch.cuda.synchronize()
+    print("served", st.as_dict(), flush=True)
+    assert st.requests == 40
+    assert len({r.M for r in reqs}) == 4
+    assert max(r.n for r in reqs) > (1 << 22)
+    sizes = {}
+    for r in reqs:
+        sizes.setdefault(r.batch, []).append(r.n)
+    # a request above 2^20 nodes went through the gather form with others
+    assert any(len(v) > 1 and max(v) > (1 << 20) for v in sizes.values())
+    for r in reqs:
+        assert r.status == 0
+        h, out = _alone(torch, r)
+        assert r.new_head == h, r.rid
+        assert torch.equal(r.out, out), r.rid
+    dt = {8: np.uint8, 16: np.uint16, 32: np.uint32, 64: np.uint64}
+    for M in (8, 16, 32, 64):
+        cand = [r for r in reqs if r.M == M and r.n <= (1 << 23)]
+        r = max(cand, key=lambda x: x.n)
+        print("oracle check M=%d n=%d" % (M, r.n), flush=True)
+        nxt = r.next.cpu().numpy().view(np.uint32)
+        keys = r.keys.cpu().numpy().view(dt[M])
+        eh, enext = oracle_mod.sort_list(r.head, nxt, keys, M, 4 if M == 8 else 8)
+        assert r.new_head == eh
+        assert np.array_equal(r.out.cpu().numpy().view(np.uint32), enext)

@@ -405,3 +405,34 @@ def test_repair_prev_hand_case_and_errors(oracle_mod):
     with pytest.raises(ValueError):
         oracle_mod.repair_prev(0, np.array([5, NIL], dtype=np.uint32))  # index out of range
     assert oracle_mod.repair_prev(NIL, np.zeros(0, dtype=np.uint32)).shape == (0,)
+
+
+@pytest.mark.parametrize("M,K", [(8, 4), (16, 2), (32, 8), (32, 4), (64, 8)])
+def test_threaded_variant_against_numpy(oracle_mod, M, K):
+    """The multi-threaded form (top levels split on the caller's thread, the
+    groups below sorted on worker threads and joined in pattern order) gives
+    the definition's result: numpy's stable argsort of the list order, either
+    direction, for any thread count; heavy ties included."""
+    rng = inputs.rng_for(660 + M + K)
+    for n, threads in [(1, 1), (2, 3), (300, 2), (20000, 5), (100003, 0)]:
+        nxt, head, order = inputs.random_list(n, rng)
+        keys = inputs.uniform_keys(n, M, rng)
+        keys[::3] = keys[0]
+        h, out = oracle_mod.sort_list_threads(head, nxt, keys, M, K, threads=threads)
+        exp = order[np.argsort(keys[order], kind="stable")]
+        assert h == exp[0] and walk(h, out) == exp.tolist()
+        h, out = oracle_mod.sort_list_threads(head, nxt, keys, M, K,
+                                              flags=oracle_mod.FLAG_DESCENDING, threads=threads)
+        expd = order[np.argsort(~keys[order], kind="stable")]
+        assert h == expd[0] and walk(h, out) == expd.tolist()
+
+
+def test_threaded_variant_rejections(oracle_mod):
+    nxt, head, _ = inputs.random_list(10, inputs.rng_for(3))
+    keys = np.arange(10, dtype=np.uint32)
+    for f in (oracle_mod.FLAG_SIGNED, oracle_mod.FLAG_FLOAT, oracle_mod.FLAG_LIFO):
+        assert oracle_mod.sort_list_threads(head, nxt, keys, 32, 8, flags=f)[0] == -1
+    assert oracle_mod.sort_list_threads(head, nxt, keys, 32, 3)[0] == -1
+    bad = nxt.copy()
+    bad[head] = head
+    assert oracle_mod.sort_list_threads(head, bad, keys, 32, 8)[0] == -2
