@@ -32,7 +32,8 @@
  * Errors are negative return values:
  *   PBIT_EINVAL     bad argument found on the host (no device work queued):
  *                   M not in {8,16,32,64}, K not in {0,1,2,4,8} or not
- *                   dividing M, n >= 2^32 - 1, head >= n, null pointer,
+ *                   dividing M (K = 0: the tuning table picks, see
+ *                   pbit_tune_set), n >= 2^32 - 1, head >= n, null pointer,
  *                   an unknown flag bit or PBIT_SIGNED with PBIT_FLOAT,
  *                   workspace too small (see PBIT_ENOMEM);
  *   PBIT_EMALFORMED found on the device: an index >= n, a cycle, or a list
@@ -241,6 +242,29 @@ int pbit_repair_prev_async(const uint32_t *d_heads, uint32_t num_lists, const ui
  * previous value.
  */
 uint32_t pbit_set_lookback_spin_limit(uint32_t sleeps);
+
+/*
+ * Tuning (Sec. 10 weighs the pattern length K against the work per pass).
+ * When K = 0 is passed, the library picks K, and every many-list sort picks
+ * its short-list cutoff, from a table of measured choices: an entry applies
+ * to sorts of its kind (0: one list, 1: many lists) and key width M whose
+ * node count (for many lists: the total) is at most n_max; the entry with the
+ * smallest such n_max wins, else K = 8 (4 for M = 8) and cutoff 2048.  Lists
+ * of at most `cutoff` nodes in a many-list sort are each sorted by one
+ * workgroup in on-chip memory; cutoff is 1024, 2048 or 4096.  The table is
+ * built in (from device measurements) and process-wide.
+ *   pbit_tune_set     adds or replaces the entry (kind, M, n_max); returns
+ *                     PBIT_OK, PBIT_EINVAL (kind > 1, K not in {1,2,4,8} or
+ *                     not dividing M, bad cutoff) or PBIT_ENOMEM (table full)
+ *   pbit_tune_reset   restores the built-in table
+ *   pbit_tune_lookup  the K and cutoff a sort of that kind, M and size gets
+ * Workspace sizes depend on K only, never on the cutoff; a change of the
+ * table between pbit_lists_workspace_bytes(.., K = 0) and the sort may change
+ * K and so make the workspace too small (PBIT_ENOMEM).
+ */
+int pbit_tune_set(uint32_t kind, uint32_t M, uint64_t n_max, uint32_t K, uint32_t cutoff);
+void pbit_tune_reset(void);
+int pbit_tune_lookup(uint32_t kind, uint32_t M, uint64_t n, uint32_t *K, uint32_t *cutoff);
 
 /* Human-readable text for a status code. */
 const char *pbit_status_string(int code);

@@ -56,6 +56,12 @@ _SIGNATURES = {
         ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
         ctypes.c_void_p, ctypes.c_void_p]),
     "pbit_set_lookback_spin_limit": (ctypes.c_uint32, [ctypes.c_uint32]),
+    "pbit_tune_set": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
+                                     ctypes.c_uint32, ctypes.c_uint32]),
+    "pbit_tune_reset": (None, []),
+    "pbit_tune_lookup": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
+                                        ctypes.POINTER(ctypes.c_uint32),
+                                        ctypes.POINTER(ctypes.c_uint32)]),
     "pbit_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "pbit_version": (ctypes.c_char_p, []),
 }
@@ -86,6 +92,24 @@ def status_string(code: int) -> str:
 
 def version() -> str:
     return load().pbit_version().decode()
+
+
+def tune_set(kind: int, M: int, n_max: int, K: int, cutoff: int) -> int:
+    """Add or replace a tuning entry (kind 0: one list, 1: many lists)."""
+    return int(load().pbit_tune_set(int(kind), int(M), int(n_max), int(K), int(cutoff)))
+
+
+def tune_reset() -> None:
+    load().pbit_tune_reset()
+
+
+def tune_lookup(kind: int, M: int, n: int):
+    """(K, cutoff) the library picks for a sort of this kind, width and size."""
+    k, c = ctypes.c_uint32(0), ctypes.c_uint32(0)
+    st = load().pbit_tune_lookup(int(kind), int(M), int(n), ctypes.byref(k), ctypes.byref(c))
+    if st != OK:
+        raise ValueError("bad tuning query")
+    return int(k.value), int(c.value)
 
 
 def set_lookback_spin_limit(sleeps: int) -> int:

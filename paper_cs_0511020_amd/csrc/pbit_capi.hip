@@ -53,34 +53,85 @@ static uint32_t level0_cap(uint64_t n, uint32_t reg)
     return reg;
 }
 
-// Pattern width when the caller leaves it to the library.
-static uint32_t default_k(uint32_t M) { return M == 8 ? 4u : 8u; }
+// ---------------------------------------------------------------- tuning
+// Choices the caller leaves to the library (K = 0; the short-list cutoff of
+// many-list sorts).  An entry applies to sorts of its kind (0: one list, 1:
+// many lists) and key width whose node count is at most n_max; the first
+// such entry in order of n_max wins.  The built-in table comes from device
+// measurements (pbit_tuning.h, written by the package's tuner);
+// pbit_tune_set adds or replaces entries at run time.
+struct TuneEntry {
+    uint32_t kind, M;
+    uint64_t n_max;
+    uint32_t K, cutoff;
+};
+#include "pbit_tuning.h"
+
+constexpr int kMaxTune = 128;
+static std::mutex g_tune_mu;
+static TuneEntry g_tune[kMaxTune];
+static int g_ntune = -1;  // -1: the built-in table not yet loaded
+
+static void tune_init_locked()
+{
+    if (g_ntune >= 0)
+        return;
+    g_ntune = 0;
+    for (const TuneEntry& t : kBuiltinTuning)
+        if (g_ntune < kMaxTune)
+            g_tune[g_ntune++] = t;
+}
+
+static bool valid_cutoff(uint32_t c) { return c == 1024 || c == 2048 || c == 4096; }
+
+// K (when 0 is passed) and the cutoff for a sort of this kind, width and size.
+static void tune_lookup(uint32_t kind, uint32_t M, uint64_t n, uint32_t* K, uint32_t* cutoff)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    tune_init_locked();
+    const TuneEntry* best = nullptr;
+    for (int i = 0; i < g_ntune; i++) {
+        const TuneEntry& t = g_tune[i];
+        if (t.kind == kind && t.M == M && n <= t.n_max && (!best || t.n_max < best->n_max))
+            best = &t;
+    }
+    *K = best ? best->K : (M == 8 ? 4u : 8u);
+    *cutoff = best ? best->cutoff : 2048u;
+}
+
+static bool valid_k(uint32_t M, uint32_t K)
+{
+    if (M != 8 && M != 16 && M != 32 && M != 64)
+        return false;
+    if (K != 1 && K != 2 && K != 4 && K != 8)
+        return false;
+    return (M % K) == 0;
+}
 
 static bool valid_shape(uint32_t M, uint32_t K)
 {
     if (M != 8 && M != 16 && M != 32 && M != 64)
         return false;
-    if (K != 0 && K != 1 && K != 2 && K != 4 && K != 8)
-        return false;
-    const uint32_t k = K ? K : default_k(M);
-    return (M % k) == 0;
+    return K == 0 || valid_k(M, K);
 }
 
-// Regions every sort uses: header, histograms, look-back words, packed
-// nodes, the two list-order buffers and the level-0 chain arrays.
-static bool plan_common(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, uint32_t lid_passes,
-                        size_t lw_bytes, uint64_t level0_chains, uint32_t cap, Plan* P, size_t& off)
+// Regions every sort uses: header, histograms, look-back words (and, for
+// many lists, the per-segment digit counts: the zeroed region ends there),
+// packed nodes, the two list-order buffers and the level-0 chain arrays.
+// K is resolved (not 0).
+static bool plan_common(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, size_t lw_bytes,
+                        uint64_t level0_chains, uint32_t cap, size_t lcnt_bytes, Plan* P,
+                        size_t& off)
 {
-    if (!valid_shape(M, K) || (flags & ~(uint32_t)(PBIT_DESCENDING | PBIT_SIGNED | PBIT_FLOAT)) != 0 ||
+    if (!valid_k(M, K) || (flags & ~(uint32_t)(PBIT_DESCENDING | PBIT_SIGNED | PBIT_FLOAT)) != 0 ||
         ((flags & PBIT_SIGNED) && (flags & PBIT_FLOAT)))
         return false;
     P->n = n;
     P->M = M;
-    P->K = K ? K : default_k(M);
+    P->K = K;
     P->RB = P->K;
     P->radix = 1u << P->K;
-    P->key_passes = M / P->K;
-    P->passes = P->key_passes + lid_passes;
+    P->passes = M / P->K;
     if (P->passes > (uint32_t)kMaxPasses)
         return false;
     P->flags = flags;
@@ -98,6 +149,8 @@ static bool plan_common(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, uint
     off = align_up(off + (size_t)P->passes * P->radix * 4);
     P->o_look = off;
     off = align_up(off + (size_t)P->passes * P->tiles * P->radix * lw_bytes);
+    P->o_lcnt = off;
+    off = align_up(off + lcnt_bytes);
     P->zero_end = off;
     P->o_nodes = off;
     off = align_up(off + n * node_bytes(P->key_bytes));
@@ -132,9 +185,13 @@ bool make_plan(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, Plan* P)
     memset(P, 0, sizeof(*P));
     if (n > PBIT_MAX_NODES || !valid_shape(M, K))
         return false;
+    if (K == 0) {
+        uint32_t cut;
+        tune_lookup(0, M, n, &K, &cut);
+    }
     if (n == 0) {
         size_t off;
-        if (!plan_common(0, M, K, flags, 0, 4, 0, 0, P, off))
+        if (!plan_common(0, M, K, flags, 4, 0, 0, 0, P, off))
             return false;
         P->total = 256;
         return true;
@@ -145,7 +202,7 @@ bool make_plan(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, Plan* P)
     // 2^30 nodes on the words are 64 bits wide
     const size_t lw_bytes = n >= (1ull << 30) ? 8 : 4;
     size_t off = 0;
-    if (!plan_common(n, M, K, flags, 0, lw_bytes, 1 + ceil_div(n, 1ull << kLog0), cap, P, off))
+    if (!plan_common(n, M, K, flags, lw_bytes, 1 + ceil_div(n, 1ull << kLog0), cap, 0, P, off))
         return false;
     int k = 1;
     uint64_t m = P->lv[0].n_static;
@@ -168,39 +225,71 @@ bool make_plan(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, Plan* P)
     return true;
 }
 
-static uint32_t bits_for(uint64_t x)
-{
-    uint32_t b = 0;
-    while (x) {
-        b++;
-        x >>= 1;
-    }
-    return b;
-}
-
-// Workspace layout for num_lists lists over n nodes in total.
+// Workspace layout for num_lists lists over n nodes in total.  The regions
+// that depend on how many lists exceed the cutoff are sized for the smallest
+// cutoff (kMinSegLen), so a workspace stays large enough whatever cutoff the
+// tuning table gives later.
 bool make_plan_lists(uint64_t n, uint32_t num_lists, uint32_t M, uint32_t K, uint32_t flags,
                      Plan* P)
 {
     memset(P, 0, sizeof(*P));
-    if (num_lists == 0 || n >= (uint64_t)PBIT_NIL || !valid_shape(M, K))
+    // one workgroup per list sorts the short ones: the list count is a grid size
+    if (num_lists == 0 || num_lists > 0x7FFFFFFFu || n >= (uint64_t)PBIT_NIL ||
+        !valid_shape(M, K))
         return false;
-    const uint32_t k = K ? K : default_k(M);
-    const uint32_t lid_passes = (uint32_t)ceil_div(bits_for(num_lists - 1) ? bits_for(num_lists - 1) : 1, k);
+    uint32_t Kt, cutoff;
+    tune_lookup(1, M, n, &Kt, &cutoff);
+    if (K == 0)
+        K = Kt;
+    if (!valid_k(M, K) || !valid_cutoff(cutoff))
+        return false;
     const uint32_t reg = reg_entries(M / 8);
     const uint32_t cap = level0_cap(n, reg);
     const uint64_t chains0 = (uint64_t)num_lists + ceil_div(n, 1ull << kLog0);
     if (chains0 >= (uint64_t)PBIT_NIL)
         return false;
+    uint64_t seg_max = n / (kMinSegLen + 1);
+    if (seg_max > num_lists)
+        seg_max = num_lists;
+    if (seg_max == 0)
+        seg_max = 1;
+    const uint64_t seg_chunks = ceil_div(seg_max, kSegChunk);
+    const uint32_t passes = M / K, radix = 1u << K;
+    const size_t lcnt_bytes = (size_t)passes * seg_max * radix * 4;
+    const size_t lw_bytes = n >= (1ull << 30) ? 8 : 4;
     size_t off = 0;
-    if (!plan_common(n, M, K, flags, lid_passes, 8, chains0, cap, P, off))
+    if (!plan_common(n, M, K, flags, lw_bytes, chains0, cap, lcnt_bytes, P, off))
         return false;
     P->num_lists = num_lists;
     P->log_block = 8;
+    P->cutoff = cutoff;
+    P->seg_max = (uint32_t)seg_max;
+    P->seg_chunks = (uint32_t)seg_chunks;
+    // a pack block's chunk meets at most chunk / (cutoff + 1) + 2 segments
+    uint64_t chunk = (uint64_t)(kPackSlots - 2) * (cutoff + 1);
+    if (chunk > 16384)
+        chunk = 16384;
+    P->pack_chunk = (uint32_t)(chunk & ~255ull);
     P->o_table = off;
     off = align_up(off + (ceil_div(n, 1ull << P->log_block) + 1) * 4);
     P->o_headbits = off;  // cleared by its own launch at the start of every sort
     off = align_up(off + (ceil_div(n, 32) + 1) * 4);
+    P->o_lseg = off;
+    off = align_up(off + ((size_t)num_lists + 1) * 4);
+    P->o_segl = off;
+    off = align_up(off + seg_max * 4);
+    P->o_coff = off;
+    off = align_up(off + (seg_max + 1) * 4);
+    P->o_ctable = off;
+    off = align_up(off + (ceil_div(n, 1ull << kSegLog) + 1) * 4);
+    P->o_lbase = off;
+    off = align_up(off + lcnt_bytes);
+    P->o_csum = off;
+    off = align_up(off + (size_t)passes * seg_chunks * radix * 4);
+    P->o_snext = off;
+    off = align_up(off + n * 4);
+    P->o_shead = off;
+    off = align_up(off + (size_t)num_lists * 4);
     int lv = 1;
     uint64_t m = chains0;
     while (m > num_lists) {
@@ -363,7 +452,9 @@ extern "C" int pbit_repair_prev_async(const uint32_t* d_heads, uint32_t num_list
 extern "C" const char* pbit_stage_name(int stage)
 {
     static const char* names[] = {"zero", "pack", "walk0", "walk_up", "base", "down",
-                                  "unchain", "schedule", "digit_pass", "relink", "walk2", "end"};
+                                  "unchain", "schedule", "digit_pass", "relink", "plan",
+                                  "small_lists", "bases", "end"};
+    static_assert(sizeof(names) / sizeof(names[0]) == kStageCount + 1, "stage names");
     if (stage < 0 || stage > (int)kStageCount)
         return "unknown";
     return names[stage];
@@ -392,7 +483,7 @@ extern "C" int64_t pbit_sort_list(uint32_t head, uint32_t* next, const void* key
         if (c.ws) {
             if (hipDeviceSynchronize() != hipSuccess)
                 return PBIT_EHIP;
-            hipFree(c.ws);
+            (void)hipFree(c.ws);
             c.ws = nullptr;
             c.bytes = 0;
         }
@@ -499,6 +590,43 @@ extern "C" int pbit_sort_lists_profiled(const uint32_t* d_heads, const uint64_t*
                                    &prof);
     *n_recorded = prof.count;
     return st;
+}
+
+extern "C" int pbit_tune_set(uint32_t kind, uint32_t M, uint64_t n_max, uint32_t K,
+                             uint32_t cutoff)
+{
+    if (kind > 1 || !valid_k(M, K) || !valid_cutoff(cutoff))
+        return PBIT_EINVAL;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    tune_init_locked();
+    for (int i = 0; i < g_ntune; i++) {
+        TuneEntry& t = g_tune[i];
+        if (t.kind == kind && t.M == M && t.n_max == n_max) {
+            t.K = K;
+            t.cutoff = cutoff;
+            return PBIT_OK;
+        }
+    }
+    if (g_ntune >= kMaxTune)
+        return PBIT_ENOMEM;
+    g_tune[g_ntune++] = TuneEntry{kind, M, n_max, K, cutoff};
+    return PBIT_OK;
+}
+
+extern "C" void pbit_tune_reset(void)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_ntune = -1;
+    tune_init_locked();
+}
+
+extern "C" int pbit_tune_lookup(uint32_t kind, uint32_t M, uint64_t n, uint32_t* K,
+                                uint32_t* cutoff)
+{
+    if (kind > 1 || !K || !cutoff || !valid_shape(M, 0))
+        return PBIT_EINVAL;
+    tune_lookup(kind, M, n, K, cutoff);
+    return PBIT_OK;
 }
 
 extern "C" uint32_t pbit_set_lookback_spin_limit(uint32_t sleeps)

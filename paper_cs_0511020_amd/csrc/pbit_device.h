@@ -239,6 +239,20 @@ template <typename KeyT> struct GatherSrc {
     }
 };
 
+// The order-preserving key transform of the flags.  Floating-point keys
+// (sign-magnitude): a negative pattern is inverted whole, a non-negative one
+// gets its sign bit set, so unsigned order of the result is the numeric order
+// (float_sel is all ones or zero).  Then the XOR mask: the sign bit for
+// two's-complement keys, all bits for descending order.
+template <typename KeyT>
+__device__ __forceinline__ KeyT transform_key(KeyT k, KeyT float_sel, KeyT xor_mask)
+{
+    constexpr uint32_t W = sizeof(KeyT) * 8;
+    const KeyT neg = (KeyT)((KeyT)0 - (KeyT)(k >> (W - 1)));
+    k ^= (KeyT)((KeyT)(neg | (KeyT)((KeyT)1 << (W - 1))) & float_sel);
+    return (KeyT)(k ^ xor_mask);
+}
+
 // Sources whose next[] and keys[] can be read four nodes at a time with
 // 16-byte loads (when both arrays are 16-byte aligned).
 template <class Src> struct Loads4 { static constexpr bool value = false; };
@@ -268,15 +282,7 @@ __global__ __launch_bounds__(256) void k_pack(Src src, uint32_t n, KeyT float_se
     // one node: key transform, hashes, NIL count, histograms; returns the
     // transformed key (the caller writes the record)
     auto take = [&](size_t i, uint32_t nx, KeyT k) -> KeyT {
-        // Floating-point keys (sign-magnitude): a negative pattern is inverted
-        // whole, a non-negative one gets its sign bit set, so unsigned order of
-        // the result is the numeric order.  float_sel is all ones or zero.
-        {
-            constexpr uint32_t W = sizeof(KeyT) * 8;
-            const KeyT neg = (KeyT)((KeyT)0 - (KeyT)(k >> (W - 1)));
-            k ^= (KeyT)((KeyT)(neg | (KeyT)((KeyT)1 << (W - 1))) & float_sel);
-        }
-        k ^= xor_mask;
+        k = transform_key<KeyT>(k, float_sel, xor_mask);
         if (nx == kNil) {
             nils++;
         } else {
@@ -481,21 +487,39 @@ __global__ __launch_bounds__(256) void k_unchain(const uint2* __restrict__ chain
 }
 
 // ---------------------------------------------------------------- schedule
-// Per pass: exclusive scan of the digit counts (global digit bases), whether
-// the pass is the identity (every element has the same digit: the paper's
-// empty groups), which ping-pong buffer it reads, and whether it must still
-// write keys (only while a later key pass runs).  Passes [0, key_passes) split
-// on key patterns, later passes on list ids.
-// The schedule as a block-level routine (256 threads, radix <= 256): its own
-// launch in the batched path, one extra block of the level-0 walk for one list.
+// Buffers of each pass: the list order starts as (key, node) pairs A; passes
+// go pairs to pairs in ping-pong, and the last pass that runs writes node
+// indices only.  Skipped passes (the identity) leave the buffers as they are.
+__device__ __forceinline__ void assign_kinds(const uint32_t* skip, uint32_t passes, Header* hdr)
+{
+    int last = -1;
+    for (uint32_t p = 0; p < passes; p++)
+        if (!skip[p])
+            last = (int)p;
+    uint32_t cur = kBufPairsA;
+    for (uint32_t p = 0; p < passes; p++) {
+        PassSched ps = hdr->sched[p];
+        ps.skip = skip[p];
+        ps.in_kind = cur;
+        ps.out_kind = (int)p == last ? kBufIdxA : (cur == kBufPairsA ? kBufPairsB : kBufPairsA);
+        if (!ps.skip)
+            cur = ps.out_kind;
+        hdr->sched[p] = ps;
+    }
+    hdr->final_kind = cur;
+}
+
+// Per pass (one list): exclusive scan of the digit counts (global digit
+// bases), whether the pass is the identity (every element has the same
+// digit: the paper's empty groups), whether one digit is frequent enough to
+// rank by ballots, and the buffers.  A block-level routine (256 threads,
+// radix <= 256): one extra block of the level-0 walk.
 __device__ __forceinline__ void schedule_body(const uint32_t* __restrict__ hist,
                                               uint32_t* __restrict__ dbase, uint32_t passes,
-                                              uint32_t key_passes, uint32_t n, uint32_t radix,
-                                              Header* hdr)
+                                              uint32_t n, uint32_t radix, Header* hdr)
 {
     __shared__ uint32_t s_v[256];
     __shared__ uint32_t s_skip[kMaxPasses];
-    __shared__ uint32_t s_skew[kMaxPasses];
     const uint32_t tid = threadIdx.x;
     for (uint32_t p = 0; p < passes; p++) {
         uint32_t v = 0;
@@ -518,60 +542,47 @@ __device__ __forceinline__ void schedule_body(const uint32_t* __restrict__ hist,
                 sum += x;
             }
             s_skip[p] = any_full ? 1u : 0u;
-            s_skew[p] = any_heavy ? 1u : 0u;
+            hdr->sched[p].ballot = any_heavy ? 1u : 0u;
         }
         __syncthreads();
         if (tid < radix)
             dbase[p * radix + tid] = s_v[tid];
         __syncthreads();
     }
-    if (tid == 0) {
-        // The list order starts as (key, node) pairs A.  Key passes go pairs to
-        // pairs; the last one that runs writes (list id, node) pairs when
-        // list-id passes follow, else node indices.  List-id passes go list-id
-        // pairs to list-id pairs, the last one that runs to node indices.
-        // (When every key pass was skipped the first list-id pass reads pairs A
-        // and looks the list ids up itself.)
-        int last_key = -1, last_lid = -1;
-        for (uint32_t p = 0; p < passes; p++) {
-            if (s_skip[p])
-                continue;
-            if (p < key_passes)
-                last_key = (int)p;
-            else
-                last_lid = (int)p;
-        }
-        uint32_t cur = kBufPairsA;
-        for (uint32_t p = 0; p < passes; p++) {
-            PassSched ps;
-            ps.skip = s_skip[p];
-            ps.in_kind = cur;
-            ps.ballot = s_skew[p];
-            // the other half of the ping-pong memory, in either pair format
-            const bool in_a = cur == kBufPairsA || cur == kBufLidA;
-            if (p < key_passes) {
-                if ((int)p == last_key)
-                    ps.out_kind = last_lid >= 0 ? (in_a ? kBufLidB : kBufLidA) : kBufIdxA;
-                else
-                    ps.out_kind = in_a ? kBufPairsB : kBufPairsA;
-            } else {
-                ps.out_kind = (int)p == last_lid ? kBufIdxA : (in_a ? kBufLidB : kBufLidA);
-            }
-            if (!ps.skip)
-                cur = ps.out_kind;
-            hdr->sched[p] = ps;
-        }
-        hdr->final_kind = cur;
-    }
+    if (tid == 0)
+        assign_kinds(s_skip, passes, hdr);
 }
 
 template <int RB>
 __global__ __launch_bounds__(256) void k_schedule(const uint32_t* __restrict__ hist,
                                                   uint32_t* __restrict__ dbase, uint32_t passes,
-                                                  uint32_t key_passes, uint32_t n, Header* hdr)
+                                                  uint32_t n, Header* hdr)
 {
-    schedule_body(hist, dbase, passes, key_passes, n, 1u << RB, hdr);
+    schedule_body(hist, dbase, passes, n, 1u << RB, hdr);
 }
+
+// ---------------------------------------------------------------- segments
+// Many lists sorted together: the lists' elements sit in one array of
+// positions, list s at [coff[s], coff[s+1]) (segments, in list order).
+// table[b] is the segment holding position b << kSegLog; lbase is a pass's
+// per-segment digit base table ([segment][radix], see the digit pass).
+struct SegMap {
+    const uint32_t* table;
+    const uint32_t* coff;
+    const uint32_t* lbase;
+};
+
+__device__ __forceinline__ uint32_t seg_of(const SegMap& sm, uint32_t pos, uint32_t nseg)
+{
+    uint32_t s = min(sm.table[pos >> kSegLog], nseg - 1u);
+    while (s + 1 < nseg && sm.coff[s + 1] <= pos)
+        s++;
+    return s;
+}
+
+// Segments one digit-pass tile may span: a tile holds at most 8192 elements
+// and every segment more than kMinSegLen, so at most 8192 / 1025 + 2 = 9.
+constexpr uint32_t kTileSegs = 16;
 
 // ---------------------------------------------------------------- digit pass
 // One stable split on the pattern at bit `shift`.  A tile of BLOCK * ITEMS
@@ -588,10 +599,19 @@ __global__ __launch_bounds__(256) void k_schedule(const uint32_t* __restrict__ h
 // waits too long on a predecessor counts that predecessor's digit in its
 // input itself, so no tile ever waits on a tile that has not been scheduled.
 //
+// An element's destination is base + P_d(j), where P_d(j) is the number of
+// elements before position j with the same digit d (local rank plus the
+// look-back prefix).  For one list the base is the digit's global start
+// dbase[d].  For many lists in segments (SEG), each list must stay in its own
+// range: list s's element with digit d goes to
+//   coff[s] + #(list s elements with digit < d) + #(list s elements with
+//   digit d before it)
+// = lbase[s][d] + P_d(j), with lbase[s][d] = coff[s] + (digit-d exclusive
+// count inside list s) - P_d(coff[s]) (wrapping 32-bit arithmetic), built
+// from per-list digit counts before the passes.
+//
 // LW is the look-back word: 2 flag bits over a 30-bit count (uint32_t, for
-// n < 2^30) or 2 flag bits over a 32-bit count (uint64_t).  With LID the
-// digit is taken from the list id of the node (many-list sorts); keys are
-// then neither read nor written.
+// n < 2^30) or 2 flag bits over a 32-bit count (uint64_t).
 template <typename LW> struct Look;
 template <> struct Look<uint32_t> {
     static constexpr uint32_t AGG = 1u << 30, PREFIX = 2u << 30, MASK = (1u << 30) - 1u;
@@ -602,15 +622,13 @@ template <> struct Look<uint64_t> {
 
 template <typename SKey> struct KV { SKey key; uint32_t idx; };
 
-
-template <typename KeyT, int RB, int BLOCK, int ITEMS, typename LW, bool LID>
+template <typename KeyT, int RB, int BLOCK, int ITEMS, typename LW, bool SEG>
 __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_pass(
-    uint32_t pass, uint32_t shift, uint32_t n, Pair<KeyT>* __restrict__ pairsA,
+    uint32_t pass, uint32_t shift, uint32_t n_all, Pair<KeyT>* __restrict__ pairsA,
     Pair<KeyT>* __restrict__ pairsB, uint32_t* __restrict__ idxA, uint32_t* __restrict__ idxB,
-    const uint32_t* __restrict__ dbase, LW* __restrict__ look, Header* hdr, LidMap lm,
+    const uint32_t* __restrict__ dbase, LW* __restrict__ look, Header* hdr, SegMap sm,
     uint32_t spin_limit)
 {
-    using SKey = typename std::conditional<LID, uint32_t, KeyT>::type;
     using LK = Look<LW>;
     constexpr uint32_t RADIX = 1u << RB;
     constexpr uint32_t WAVES = BLOCK / 64;
@@ -619,10 +637,13 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
     __shared__ uint32_t s_count[RADIX];
     __shared__ uint32_t s_start[RADIX];
     __shared__ uint32_t s_delta[RADIX];
-    __shared__ __attribute__((aligned(16))) KV<SKey> s_kv[TILE];
+    __shared__ __attribute__((aligned(16))) KV<KeyT> s_kv[TILE];
+    // SEG: the segment of each staged element, relative to the tile's first
+    __shared__ uint8_t s_seg[SEG ? TILE : 1];
+    __shared__ uint32_t s_bound[SEG ? kTileSegs : 1];
     // during ranking the start of s_kv holds one 64-bit lane mask per digit
     // per wave (it is staged into only afterwards)
-    static_assert((size_t)WAVES * RADIX * 8 <= sizeof(KV<SKey>) * TILE, "peer masks fit in s_kv");
+    static_assert((size_t)WAVES * RADIX * 8 <= sizeof(KV<KeyT>) * TILE, "peer masks fit in s_kv");
     unsigned long long* s_mask = (unsigned long long*)s_kv;
 
     if (hdr->status != 0)
@@ -630,17 +651,13 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
     const PassSched ps = hdr->sched[pass];
     if (ps.skip)
         return;
-    // key passes read (key, node) pairs and write pairs, or from the last one
-    // (list id, node) pairs or node indices; list-id passes read (list id,
-    // node) pairs (or pairs A, looking list ids up, when every key pass was
-    // skipped) and write (list id, node) pairs or, from the last, node indices
-    const bool in_lid = ps.in_kind >= kBufLidA;
+    // the number of elements: the whole list, or (SEG) the lists that take
+    // the passes, known on the device only
+    const uint32_t n = SEG ? hdr->seg_nodes : n_all;
+    const uint32_t nseg = SEG ? hdr->n_segs : 0u;
     const bool out_pairs = ps.out_kind < kBufIdxA;
-    const bool out_lid = ps.out_kind >= kBufLidA;
     const Pair<KeyT>* pin = ps.in_kind == kBufPairsB ? pairsB : pairsA;
-    const uint2* lin = (const uint2*)(ps.in_kind == kBufLidB ? (const void*)pairsB : (const void*)pairsA);
     Pair<KeyT>* pout = ps.out_kind == kBufPairsB ? pairsB : pairsA;
-    uint2* lout = (uint2*)(ps.out_kind == kBufLidB ? (void*)pairsB : (void*)pairsA);
     uint32_t* iout = ps.out_kind == kBufIdxB ? idxB : idxA;
 
     const uint32_t tid = threadIdx.x;
@@ -649,50 +666,59 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
         (&s_wave[0][0])[i] = 0;
         s_mask[i] = 0ull;
     }
-    __syncthreads();
     const uint32_t q = blockIdx.x / 8u;
     const uint32_t tile = (q / kPassChunk) * (8u * kPassChunk) + (blockIdx.x % 8u) * kPassChunk +
                           q % kPassChunk;
     if ((uint64_t)tile * TILE >= (uint64_t)n)
-        return;  // the grid is rounded up to whole chunk groups
+        return;  // the grid is rounded up to whole chunk groups (and, SEG, to all nodes)
     const uint64_t tbase = (uint64_t)tile * TILE;
     const uint64_t wbase = tbase + (uint64_t)wave * (64 * ITEMS);
+    uint32_t seg0 = 0, nb = 0;
+    if constexpr (SEG) {
+        // the segments this tile spans: boundaries relative to its first one
+        seg0 = seg_of(sm, (uint32_t)tbase, nseg);
+        const uint32_t tend = (uint32_t)min<uint64_t>(tbase + TILE, (uint64_t)n);
+        if (tid < kTileSegs) {
+            const uint32_t sidx = seg0 + 1 + tid;
+            s_bound[tid] = sidx < nseg ? sm.coff[sidx] : 0xFFFFFFFFu;
+        }
+        for (uint32_t k = 0; k < kTileSegs; k++)
+            nb += (seg0 + 1 + k < nseg) && (sm.coff[seg0 + 1 + k] < tend);
+    }
+    __syncthreads();
 
-    SKey key[ITEMS];
+    KeyT key[ITEMS];
     uint32_t idx[ITEMS], dig[ITEMS], rank[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
         const uint64_t e = wbase + (uint64_t)i * 64 + lane;
         if (e < n) {
-            if constexpr (LID) {
-                if (in_lid) {
-                    const uint2 v = lin[e];
-                    key[i] = v.x;
-                    idx[i] = v.y;
-                } else {
-                    idx[i] = pin[e].idx;
-                    key[i] = list_of(lm, idx[i]);
-                }
-            } else {
-                const Pair<KeyT> v = pin[e];
-                key[i] = (SKey)pair_key<KeyT>(v);
-                idx[i] = v.idx;
-            }
+            const Pair<KeyT> v = pin[e];
+            key[i] = pair_key<KeyT>(v);
+            idx[i] = v.idx;
             dig[i] = (uint32_t)(key[i] >> shift) & (RADIX - 1u);
+            if constexpr (SEG) {
+                uint32_t sl = 0;
+                while (sl < nb && s_bound[sl] <= (uint32_t)e)
+                    sl++;
+                dig[i] |= sl << 9;
+            }
         } else {
             key[i] = 0;
             idx[i] = 0;
             dig[i] = RADIX;
         }
     }
-    // dig[i] bits: 0..8 digit (RADIX = invalid), 16..21 rank in the wave's
-    // group, 24..29 the group's first lane (which holds the LDS base)
+    // dig[i] bits: 0..8 digit (RADIX = invalid), 9..15 segment slot (SEG),
+    // 16..21 rank in the wave's group, 24..29 the group's first lane (which
+    // holds the LDS base)
     const uint64_t lt = lanemask_lt();
     unsigned long long* w_mask = s_mask + (size_t)wave * RADIX;
     const bool by_ballot = ps.ballot != 0;
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
-        const bool valid = dig[i] < RADIX;
+        const uint32_t d = dig[i] & 0x1FFu;
+        const bool valid = d < RADIX;
         // peers = the lanes of this wave whose item i has the same digit
         uint64_t peers;
         if (by_ballot) {
@@ -700,7 +726,7 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
             peers = __ballot(valid);
 #pragma unroll
             for (int b = 0; b < RB; b++) {
-                const bool bit = (dig[i] >> b) & 1u;
+                const bool bit = (d >> b) & 1u;
                 const uint64_t bb = __ballot(bit);
                 peers &= bit ? bb : ~bb;
             }
@@ -710,15 +736,15 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
             // exact however the LDS serialises lanes that hit the same word;
             // a wave's LDS operations complete in issue order.
             if (valid)
-                __hip_atomic_fetch_or(&w_mask[dig[i]], 1ull << lane, __ATOMIC_RELAXED,
+                __hip_atomic_fetch_or(&w_mask[d], 1ull << lane, __ATOMIC_RELAXED,
                                       __HIP_MEMORY_SCOPE_WAVEFRONT);
             __builtin_amdgcn_wave_barrier();
-            peers = valid ? (uint64_t)__hip_atomic_load(&w_mask[dig[i]], __ATOMIC_RELAXED,
+            peers = valid ? (uint64_t)__hip_atomic_load(&w_mask[d], __ATOMIC_RELAXED,
                                                         __HIP_MEMORY_SCOPE_WAVEFRONT)
                           : 0ull;
             __builtin_amdgcn_wave_barrier();
             if (valid)
-                __hip_atomic_store(&w_mask[dig[i]], 0ull, __ATOMIC_RELAXED,
+                __hip_atomic_store(&w_mask[d], 0ull, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WAVEFRONT);
             __builtin_amdgcn_wave_barrier();
         }
@@ -726,7 +752,7 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
         const uint32_t first = valid ? (uint32_t)(__ffsll((unsigned long long)peers) - 1) : lane;
         uint32_t base = 0;
         if (valid && below == 0)
-            base = atomicAdd(&s_wave[wave][dig[i]], (uint32_t)__popcll(peers));
+            base = atomicAdd(&s_wave[wave][d], (uint32_t)__popcll(peers));
         rank[i] = base;
         dig[i] |= (below << 16) | (first << 24);
     }
@@ -801,16 +827,8 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
                     const uint64_t b0 = (uint64_t)j * TILE;
                     const uint64_t b1 = min<uint64_t>(b0 + TILE, (uint64_t)n);
                     uint32_t c = 0;
-                    for (uint64_t q = b0; q < b1; q++) {
-                        uint32_t x;
-                        if constexpr (LID)
-                            x = in_lid ? lin[q].x : list_of(lm, pin[q].idx);
-                        else
-                            x = (uint32_t)(pair_key<KeyT>(pin[q]) >> shift);
-                        if constexpr (LID)
-                            x >>= shift;
-                        c += (x & (RADIX - 1u)) == d;
-                    }
+                    for (uint64_t q = b0; q < b1; q++)
+                        c += ((uint32_t)(pair_key<KeyT>(pin[q]) >> shift) & (RADIX - 1u)) == d;
                     excl += c;
                     j--;
                     spins = 0;
@@ -824,18 +842,22 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
             }
             st_agent(&look[(size_t)tile * RADIX + d], LK::PREFIX | (LW)(excl + s_count[d]));
         }
-        // wrapping u32 arithmetic: position = j + (base - local start)
-        s_delta[d] = dbase[d] + excl - s_start[d];
+        // wrapping u32 arithmetic: position = j + (base - local start), the
+        // base of SEG lists added per element
+        s_delta[d] = (SEG ? 0u : dbase[d]) + excl - s_start[d];
     }
     // stage the tile in LDS grouped by digit (stable)
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
-        if (dig[i] < RADIX) {
-            const uint32_t pos = s_wave[wave][dig[i]] + rank[i];
-            KV<SKey> kv;
+        const uint32_t d = dig[i] & 0x1FFu;
+        if (d < RADIX) {
+            const uint32_t pos = s_wave[wave][d] + rank[i];
+            KV<KeyT> kv;
             kv.key = key[i];
             kv.idx = idx[i];
             s_kv[pos] = kv;
+            if constexpr (SEG)
+                s_seg[pos] = (uint8_t)(dig[i] >> 9);
         }
     }
     __syncthreads();
@@ -844,14 +866,14 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
     for (int i = 0; i < ITEMS; i++) {
         const uint32_t j = tid + i * BLOCK;
         if (j < valid_n) {
-            const KV<SKey> kv = s_kv[j];
+            const KV<KeyT> kv = s_kv[j];
             const uint32_t d = (uint32_t)(kv.key >> shift) & (RADIX - 1u);
-            const uint32_t g = j + s_delta[d];
+            uint32_t g = j + s_delta[d];
+            if constexpr (SEG)
+                g += sm.lbase[(size_t)(seg0 + s_seg[j]) * RADIX + d];
             if (g < n) {
-                if (!LID && out_pairs)
-                    pout[g] = make_pair_kv<KeyT>((KeyT)kv.key, kv.idx);
-                else if (out_lid)  // the last key pass looks each node's list up once
-                    lout[g] = make_uint2(LID ? (uint32_t)kv.key : list_of(lm, kv.idx), kv.idx);
+                if (out_pairs)
+                    pout[g] = make_pair_kv<KeyT>(kv.key, kv.idx);
                 else
                     iout[g] = kv.idx;
             }

@@ -27,7 +27,19 @@ constexpr int kMaxLevels = 12;
 // Chains longer than their level-0 slot that the unchain launch's first
 // blocks take (each further one is walked by its own chain's group).
 constexpr uint32_t kLongListMax = 16 * 256;
-constexpr int kMaxPasses = 96;
+constexpr int kMaxPasses = 64;
+// Many-list sorts.  Lists of more than a cutoff of nodes (at least
+// kMinSegLen) take the digit passes as segments of one position array; the
+// others are sorted in LDS, one workgroup each, with cutoffs of 1024, 2048 or
+// 4096 nodes.
+constexpr uint32_t kMinSegLen = 1024;
+constexpr uint32_t kMaxCutoff = 4096;
+// Lists per group of the per-list digit base scan.
+constexpr uint32_t kSegChunk = 64;
+// Segments whose digit counts one pack block keeps in LDS.
+constexpr uint32_t kPackSlots = 8;
+// Position -> segment table granularity (log2).
+constexpr uint32_t kSegLog = 8;
 // Sleeps a digit pass's look-back waits on one predecessor tile before it
 // counts that tile's digit itself (default; pbit_set_lookback_spin_limit
 // changes it, 0 makes every tile whose predecessor has not published yet
@@ -39,12 +51,9 @@ constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagPrefix = 2u << 30;
 constexpr uint32_t kCountMask = (1u << 30) - 1u;
 
-// List-order buffers: (key, node) pairs while key passes remain; (list id,
-// node) pairs (in the same memory, 8 bytes each) while list-id passes remain;
-// node indices alone after the last pass.
-enum BufKind : uint32_t {
-    kBufPairsA = 0, kBufPairsB = 1, kBufIdxA = 2, kBufIdxB = 3, kBufLidA = 4, kBufLidB = 5
-};
+// List-order buffers: (key, node) pairs while passes remain, node indices
+// alone after the last pass.
+enum BufKind : uint32_t { kBufPairsA = 0, kBufPairsB = 1, kBufIdxA = 2, kBufIdxB = 3 };
 
 struct PassSched {
     uint32_t skip;      // every element has the same digit: the pass is the identity
@@ -60,8 +69,11 @@ struct Header {
     uint32_t nil_count;       // next[] entries equal to NIL
     uint32_t expect_nil;      // many-list sorts: non-empty lists (one NIL each)
     uint32_t n_long;          // level-0 chains longer than their slot
-    uint32_t pad0;
+    uint32_t n_segs;          // many-list sorts: lists that take the digit passes
     uint64_t hsum[2];         // sum of h(next) over non-NIL next[] minus sum of h(i)
+    uint32_t seg_nodes;       // many-list sorts: their nodes
+    uint32_t pad1;
+    uint32_t seg_trivial[kMaxPasses];  // lists whose pattern p is one value for all nodes
     PassSched sched[kMaxPasses];
 };
 
@@ -81,7 +93,9 @@ struct LevelPlan {
 enum Stage : int32_t {
     kStageZero = 0, kStagePack, kStageWalk0, kStageWalkUp, kStageBase, kStageDown,
     kStageUnchain, kStageSchedule, kStagePass, kStageRelink,
-    kStageWalk2,  // no longer a launch of its own: the long rests run inside unchain
+    kStagePlan,   // many-list sorts: slab checks, segments, tables
+    kStageSmall,  // many-list sorts: short lists sorted in LDS
+    kStageBases,  // many-list sorts: per-list digit bases
     kStageCount
 };
 
@@ -98,16 +112,24 @@ struct Plan {
     uint64_t n;
     uint32_t M, K, RB, radix, passes, flags, key_bytes;
     uint32_t tile, tiles;
-    uint32_t key_passes;  // passes on key patterns; the rest split on list ids
     uint32_t spin_limit;  // look-back sleeps on one predecessor before the fallback
     uint32_t look64;      // 64-bit look-back words (counts of 2^30 and more)
     uint32_t num_lists;   // many-list sorts
     uint32_t log_block;   // many-list sorts: node block size of the list table
+    uint32_t cutoff;      // many-list sorts: lists of at most this many nodes sort in LDS
+    uint32_t seg_max;     // many-list sorts: most lists that can exceed the cutoff
+    uint32_t seg_chunks;  // many-list sorts: groups of kSegChunk lists in the base scan
+    uint32_t pack_chunk;  // many-list sorts: nodes per pack block
     int levels;           // walk levels; the base ranks level `levels`
     LevelPlan lv[kMaxLevels];
     size_t o_header, o_hist, o_dbase, o_look, zero_end;
     size_t o_nodes, o_pairsA, o_pairsB, o_idxA, o_idxB;
-    size_t o_table, o_headbits;  // many-list sorts
+    // many-list sorts
+    size_t o_table, o_headbits;     // node -> list, head marks
+    size_t o_lseg, o_segl, o_coff;  // list -> segment, segment -> list, segment offsets
+    size_t o_ctable;                // position -> segment
+    size_t o_lcnt, o_lbase, o_csum; // per-segment digit counts, bases, chunk sums
+    size_t o_snext, o_shead;        // results of the lists sorted in LDS
     size_t total;
 };
 

@@ -84,13 +84,13 @@ __global__ __launch_bounds__(256) void k_walk0(const NodeRec<KeyT>* __restrict__
                                                uint32_t walk_blocks,
                                                const uint32_t* __restrict__ hist,
                                                uint32_t* __restrict__ dbase, uint32_t passes,
-                                               uint32_t key_passes, uint32_t radix)
+                                               uint32_t radix)
 {
     constexpr uint32_t C = SegLen<KeyT>::value;
     if (blockIdx.x == walk_blocks) {
         // one extra block: the pass schedule needs only pack's histograms, so
         // it runs beside the walk instead of as a launch of its own
-        schedule_body(hist, dbase, passes, key_passes, n, radix, hdr);
+        schedule_body(hist, dbase, passes, n, radix, hdr);
         return;
     }
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -360,7 +360,7 @@ static hipError_t launch_walk0(const Plan& P, uint32_t head, char* ws, hipStream
                        (Entry<KeyT>*)(ws + L.o_ent), (uint32_t*)(ws + L.o_resume), L.cap,
                        (uint32_t*)(ws + L.o_long), (Header*)(ws + P.o_header), walk_blocks,
                        (const uint32_t*)(ws + P.o_hist), (uint32_t*)(ws + P.o_dbase), P.passes,
-                       P.key_passes, P.radix);
+                       P.radix);
     return hipGetLastError();
 }
 
@@ -465,17 +465,17 @@ static hipError_t enqueue_after_pack(const Plan& P, uint32_t head, char* out_bas
         return e;
     if (P.look64) {
         switch (P.key_bytes) {
-        case 1: e = launch_passes<uint8_t, uint64_t>(P, ws, s, prof, LidMap{}, true); break;
-        case 2: e = launch_passes<uint16_t, uint64_t>(P, ws, s, prof, LidMap{}, true); break;
-        case 4: e = launch_passes<uint32_t, uint64_t>(P, ws, s, prof, LidMap{}, true); break;
-        default: e = launch_passes<uint64_t, uint64_t>(P, ws, s, prof, LidMap{}, true); break;
+        case 1: e = launch_passes<uint8_t, uint64_t, false>(P, ws, s, prof, true); break;
+        case 2: e = launch_passes<uint16_t, uint64_t, false>(P, ws, s, prof, true); break;
+        case 4: e = launch_passes<uint32_t, uint64_t, false>(P, ws, s, prof, true); break;
+        default: e = launch_passes<uint64_t, uint64_t, false>(P, ws, s, prof, true); break;
         }
     } else {
         switch (P.key_bytes) {
-        case 1: e = launch_passes<uint8_t, uint32_t>(P, ws, s, prof, LidMap{}, true); break;
-        case 2: e = launch_passes<uint16_t, uint32_t>(P, ws, s, prof, LidMap{}, true); break;
-        case 4: e = launch_passes<uint32_t, uint32_t>(P, ws, s, prof, LidMap{}, true); break;
-        default: e = launch_passes<uint64_t, uint32_t>(P, ws, s, prof, LidMap{}, true); break;
+        case 1: e = launch_passes<uint8_t, uint32_t, false>(P, ws, s, prof, true); break;
+        case 2: e = launch_passes<uint16_t, uint32_t, false>(P, ws, s, prof, true); break;
+        case 4: e = launch_passes<uint32_t, uint32_t, false>(P, ws, s, prof, true); break;
+        default: e = launch_passes<uint64_t, uint32_t, false>(P, ws, s, prof, true); break;
         }
     }
     if (e != hipSuccess)

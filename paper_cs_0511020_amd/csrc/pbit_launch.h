@@ -10,10 +10,27 @@ static inline void mark(Prof* prof, hipStream_t s, int32_t stage)
 {
     if (!prof || prof->count >= prof->n_events)
         return;
-    hipEventRecord((hipEvent_t)prof->events[prof->count], s);
+    (void)hipEventRecord((hipEvent_t)prof->events[prof->count], s);
     if (prof->ids)
         prof->ids[prof->count] = stage;
     prof->count++;
+}
+
+// The key transform of the flags: the mask every key is XORed with after the
+// floating-point transform (signed: the sign bit; descending: all bits), and
+// the all-ones selector of that transform.
+template <typename KeyT> static inline KeyT key_xor_mask(uint32_t flags)
+{
+    KeyT mask = 0;
+    if (flags & PBIT_SIGNED)
+        mask ^= (KeyT)((KeyT)1 << (sizeof(KeyT) * 8 - 1));
+    if (flags & PBIT_DESCENDING)
+        mask ^= (KeyT)~(KeyT)0;
+    return mask;
+}
+template <typename KeyT> static inline KeyT key_float_sel(uint32_t flags)
+{
+    return (flags & PBIT_FLOAT) ? (KeyT)~(KeyT)0 : (KeyT)0;
 }
 
 static inline hipError_t launch_zero(const Plan& P, char* ws, hipStream_t s)
@@ -28,17 +45,13 @@ static inline hipError_t launch_zero(const Plan& P, char* ws, hipStream_t s)
 template <typename KeyT, int RB, class Src>
 static hipError_t launch_pack_rb(const Plan& P, const Src& src, char* ws, hipStream_t s)
 {
-    KeyT mask = 0;
-    const KeyT float_sel = (P.flags & PBIT_FLOAT) ? (KeyT)~(KeyT)0 : (KeyT)0;
-    if (P.flags & PBIT_SIGNED)
-        mask ^= (KeyT)((KeyT)1 << (sizeof(KeyT) * 8 - 1));
-    if (P.flags & PBIT_DESCENDING)
-        mask ^= (KeyT)~(KeyT)0;
+    const KeyT mask = key_xor_mask<KeyT>(P.flags);
+    const KeyT float_sel = key_float_sel<KeyT>(P.flags);
     const uint64_t want = (P.n + 255) / 256;
     const uint32_t blocks = (uint32_t)(want < 1024 ? want : 1024);
-    const size_t shm = (size_t)P.key_passes * P.radix * sizeof(uint32_t);
+    const size_t shm = (size_t)P.passes * P.radix * sizeof(uint32_t);
     hipLaunchKernelGGL((k_pack<KeyT, RB, Src>), dim3(blocks), dim3(256), shm, s, src,
-                       (uint32_t)P.n, float_sel, mask, P.key_passes, (NodeRec<KeyT>*)(ws + P.o_nodes),
+                       (uint32_t)P.n, float_sel, mask, P.passes, (NodeRec<KeyT>*)(ws + P.o_nodes),
                        (uint32_t*)(ws + P.o_hist), (Header*)(ws + P.o_header));
     return hipGetLastError();
 }
@@ -61,21 +74,23 @@ static hipError_t launch_pack(const Plan& P, const uint32_t* next, const void* k
     return launch_pack_src<KeyT>(P, DirectSrc<KeyT>{next, (const KeyT*)keys}, ws, s);
 }
 
-// Schedule, then P.key_passes passes on key patterns and the remaining
-// passes on list ids (many-list sorts).
-template <typename KeyT, int RB, typename LW>
+// The digit passes, least-significant pattern first.  One list: the
+// schedule has run (as one extra block of the level-0 walk) unless
+// `scheduled` is false.  SEG: many lists in segments, each pass with its
+// per-segment base table (the schedule ran with the base scan).
+template <typename KeyT, int RB, typename LW, bool SEG>
 static hipError_t launch_passes_rb(const Plan& P, char* ws, hipStream_t s, Prof* prof,
-                                   const LidMap& lm, bool scheduled)
+                                   bool scheduled)
 {
     constexpr int BLOCK = PassShape<KeyT, RB>::block;
     constexpr int ITEMS = PassShape<KeyT, RB>::items;
     constexpr uint32_t RADIX = 1u << RB;
     hipError_t e;
-    if (!scheduled) {
+    if (!SEG && !scheduled) {
         mark(prof, s, kStageSchedule);
         hipLaunchKernelGGL((k_schedule<RB>), dim3(1), dim3(256), 0, s,
                            (const uint32_t*)(ws + P.o_hist), (uint32_t*)(ws + P.o_dbase),
-                           P.passes, P.key_passes, (uint32_t)P.n, (Header*)(ws + P.o_header));
+                           P.passes, (uint32_t)P.n, (Header*)(ws + P.o_header));
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }
@@ -83,21 +98,17 @@ static hipError_t launch_passes_rb(const Plan& P, char* ws, hipStream_t s, Prof*
     const uint32_t grid = (uint32_t)((P.tiles + group - 1) / group * group);
     for (uint32_t p = 0; p < P.passes; p++) {
         LW* look = (LW*)(ws + P.o_look) + (size_t)p * P.tiles * RADIX;
-        const uint32_t* dbase = (const uint32_t*)(ws + P.o_dbase) + (size_t)p * RADIX;
+        const uint32_t* dbase = SEG ? nullptr : (const uint32_t*)(ws + P.o_dbase) + (size_t)p * RADIX;
+        SegMap sm{};
+        if (SEG)
+            sm = SegMap{(const uint32_t*)(ws + P.o_ctable), (const uint32_t*)(ws + P.o_coff),
+                        (const uint32_t*)(ws + P.o_lbase) + (size_t)p * P.seg_max * RADIX};
         mark(prof, s, kStagePass);
-        if (p < P.key_passes) {
-            hipLaunchKernelGGL((k_digit_pass<KeyT, RB, BLOCK, ITEMS, LW, false>), dim3(grid),
-                               dim3(BLOCK), 0, s, p, p * RB, (uint32_t)P.n,
-                               (Pair<KeyT>*)(ws + P.o_pairsA), (Pair<KeyT>*)(ws + P.o_pairsB),
-                               (uint32_t*)(ws + P.o_idxA), (uint32_t*)(ws + P.o_idxB), dbase, look,
-                               (Header*)(ws + P.o_header), lm, P.spin_limit);
-        } else {
-            hipLaunchKernelGGL((k_digit_pass<KeyT, RB, BLOCK, ITEMS, LW, true>), dim3(grid),
-                               dim3(BLOCK), 0, s, p, (p - P.key_passes) * RB, (uint32_t)P.n,
-                               (Pair<KeyT>*)(ws + P.o_pairsA), (Pair<KeyT>*)(ws + P.o_pairsB),
-                               (uint32_t*)(ws + P.o_idxA), (uint32_t*)(ws + P.o_idxB), dbase, look,
-                               (Header*)(ws + P.o_header), lm, P.spin_limit);
-        }
+        hipLaunchKernelGGL((k_digit_pass<KeyT, RB, BLOCK, ITEMS, LW, SEG>), dim3(grid),
+                           dim3(BLOCK), 0, s, p, p * RB, (uint32_t)P.n,
+                           (Pair<KeyT>*)(ws + P.o_pairsA), (Pair<KeyT>*)(ws + P.o_pairsB),
+                           (uint32_t*)(ws + P.o_idxA), (uint32_t*)(ws + P.o_idxB), dbase, look,
+                           (Header*)(ws + P.o_header), sm, P.spin_limit);
         e = hipGetLastError();
         if (e != hipSuccess)
             return e;
@@ -105,16 +116,15 @@ static hipError_t launch_passes_rb(const Plan& P, char* ws, hipStream_t s, Prof*
     return hipSuccess;
 }
 
-// scheduled: the schedule already ran (one extra block of the single-list walk)
-template <typename KeyT, typename LW>
+template <typename KeyT, typename LW, bool SEG>
 static hipError_t launch_passes(const Plan& P, char* ws, hipStream_t s, Prof* prof,
-                                const LidMap& lm, bool scheduled = false)
+                                bool scheduled = false)
 {
     switch (P.RB) {
-    case 1: return launch_passes_rb<KeyT, 1, LW>(P, ws, s, prof, lm, scheduled);
-    case 2: return launch_passes_rb<KeyT, 2, LW>(P, ws, s, prof, lm, scheduled);
-    case 4: return launch_passes_rb<KeyT, 4, LW>(P, ws, s, prof, lm, scheduled);
-    default: return launch_passes_rb<KeyT, 8, LW>(P, ws, s, prof, lm, scheduled);
+    case 1: return launch_passes_rb<KeyT, 1, LW, SEG>(P, ws, s, prof, scheduled);
+    case 2: return launch_passes_rb<KeyT, 2, LW, SEG>(P, ws, s, prof, scheduled);
+    case 4: return launch_passes_rb<KeyT, 4, LW, SEG>(P, ws, s, prof, scheduled);
+    default: return launch_passes_rb<KeyT, 8, LW, SEG>(P, ws, s, prof, scheduled);
     }
 }
 

@@ -161,3 +161,34 @@ def test_lists_host_checks(lib):
     assert call(flags=8) == E
     assert call(flags=_lib.SIGNED | _lib.FLOAT) == E
     assert call(wsb=100) == _lib.ENOMEM
+
+
+def test_tuning_table_is_read_and_applied(lib):
+    """K = 0 takes the tuning table's choice: the workspace a K = 0 call asks
+    for equals the one for the table's K, an added entry overrides the
+    built-in one for sizes up to its n_max only, and reset restores it."""
+    _lib.tune_reset()
+    try:
+        k0, c0 = _lib.tune_lookup(0, 32, 1 << 20)
+        assert k0 in (4, 8) and c0 in (1024, 2048, 4096)
+        assert _lib.workspace_bytes(1 << 20, 32, 0) == _lib.workspace_bytes(1 << 20, 32, k0)
+        other = 12 - k0
+        assert _lib.tune_set(0, 32, 1 << 21, other, 2048) == 0
+        assert _lib.tune_lookup(0, 32, 1 << 20) == (other, 2048)
+        assert _lib.tune_lookup(0, 32, (1 << 21) + 1) == (k0, c0)
+        assert _lib.workspace_bytes(1 << 20, 32, 0) == _lib.workspace_bytes(1 << 20, 32, other)
+        kb, cb = _lib.tune_lookup(1, 16, 5000)
+        assert _lib.tune_set(1, 16, 1 << 30, 4, 4096) == 0
+        assert _lib.tune_lookup(1, 16, 5000) == (4, 4096)
+        assert (_lib.lists_workspace_bytes(1 << 20, 100, 16, 0)
+                == _lib.lists_workspace_bytes(1 << 20, 100, 16, 4))
+        # rejected entries
+        assert _lib.tune_set(2, 32, 1, 8, 2048) == _lib.EINVAL
+        assert _lib.tune_set(0, 32, 1, 3, 2048) == _lib.EINVAL
+        assert _lib.tune_set(0, 8, 1, 16, 2048) == _lib.EINVAL
+        assert _lib.tune_set(1, 32, 1, 8, 512) == _lib.EINVAL
+        _lib.tune_reset()
+        assert _lib.tune_lookup(0, 32, 1 << 20) == (k0, c0)
+        assert _lib.tune_lookup(1, 16, 5000) == (kb, cb)
+    finally:
+        _lib.tune_reset()

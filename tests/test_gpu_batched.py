@@ -102,8 +102,8 @@ def test_key_widths(oracle_mod, M, K):
         check(oracle_mod, heads, offs, nxt, fkeys, K, flags=5)
 
 
-def test_many_lists_three_id_passes(oracle_mod):
-    """More than 2^16 lists: three 8-bit passes on the list id."""
+def test_70000_tiny_lists(oracle_mod):
+    """More than 2^16 lists of 0 to 3 nodes: all sorted in LDS, many empty."""
     rng = inputs.rng_for(4301)
     lengths = rng.integers(0, 4, size=70000)
     nxt, heads, offs = inputs.slab_lists(lengths, rng)
@@ -251,3 +251,92 @@ def test_gather_form_and_its_rejections(oracle_mod):
     rejected(bad_heads, offs)
     bad_heads = list(heads); bad_heads[2] = 0       # head given for an empty list
     rejected(bad_heads, offs)
+
+
+@pytest.fixture
+def cutoff_setter():
+    """Set the short-list cutoff of many-list sorts through the tuning table;
+    the built-in table is restored afterwards."""
+    from paper_cs_0511020_amd import _lib
+
+    def set_cutoff(M, K, cutoff):
+        assert _lib.tune_set(1, M, 0xFFFFFFFF, K, cutoff) == 0
+        assert _lib.tune_lookup(1, M, 1000) == (K, cutoff)
+    yield set_cutoff
+    _lib.tune_reset()
+
+
+@pytest.mark.parametrize("cutoff", [1024, 2048, 4096])
+@pytest.mark.parametrize("M,K", [(32, 8), (8, 4), (64, 8), (16, 4)])
+def test_lists_straddling_the_cutoff(oracle_mod, cutoff_setter, cutoff, M, K):
+    """Lists one node either side of the cutoff take different paths (LDS
+    sort or segment passes); all must equal the oracle, with ties."""
+    cutoff_setter(M, K, cutoff)
+    rng = inputs.rng_for(4700 + cutoff + M + K)
+    lengths = [cutoff - 1, cutoff, cutoff + 1, 1, 0, 2 * cutoff + 7, 16, cutoff + 1, 3,
+               cutoff, 9000, 2, cutoff - 1]
+    nxt, heads, offs = inputs.slab_lists(lengths, rng)
+    keys = inputs.uniform_keys(nxt.shape[0], M, rng)
+    keys[::3] = keys[1]
+    say("straddle cutoff=%d M=%d K=%d" % (cutoff, M, K))
+    check(oracle_mod, heads, offs, nxt, keys, K)
+    check(oracle_mod, heads, offs, nxt, keys, K, flags=3 if M != 8 else 1)
+
+
+def test_tiles_spanning_many_segments(oracle_mod, cutoff_setter):
+    """Segments just above the smallest cutoff: a digit-pass tile (6144 or
+    8192 positions) spans up to 8 of them, each with its own digit bases."""
+    cutoff_setter(32, 8, 1024)
+    rng = inputs.rng_for(4801)
+    lengths = rng.integers(1025, 1300, size=300)
+    lengths[::7] = rng.integers(1, 1024, size=len(lengths[::7]))
+    nxt, heads, offs = inputs.slab_lists(lengths, rng)
+    keys = inputs.uniform_keys(nxt.shape[0], 32, rng)
+    keys[::2] = keys[5]
+    say("tiles over many segments, %d nodes" % nxt.shape[0])
+    check(oracle_mod, heads, offs, nxt, keys, 8)
+    check(oracle_mod, heads, offs, nxt, keys, 4)
+    k64 = inputs.uniform_keys(nxt.shape[0], 64, rng)
+    cutoff_setter(64, 8, 1024)
+    check(oracle_mod, heads, offs, nxt, k64, 8)
+
+
+def test_batches_of_one_path_only(oracle_mod):
+    """Every list short (no segment passes at all) or every list long."""
+    rng = inputs.rng_for(4901)
+    nxt, heads, offs = inputs.slab_lists(rng.integers(0, 2048, size=500), rng)
+    keys = rng.integers(0, 1000, size=nxt.shape[0]).astype(np.uint32)
+    check(oracle_mod, heads, offs, nxt, keys, 8)
+    nxt, heads, offs = inputs.slab_lists(rng.integers(4097, 30000, size=40), rng)
+    keys = rng.integers(0, 1000, size=nxt.shape[0]).astype(np.uint32)
+    check(oracle_mod, heads, offs, nxt, keys, 8)
+    # constant keys inside every list: every pass is skipped for the segments
+    per = np.repeat(np.arange(40, dtype=np.uint32), np.diff(offs.astype(np.int64)))
+    check(oracle_mod, heads, offs, nxt, per * np.uint32(7919), 8)
+
+
+def test_short_list_malformations_leave_outputs(cutoff_setter):
+    """A cycle, a link out of the slab, or a second list inside one short
+    list's slab: PBIT_EMALFORMED, nothing written."""
+    cutoff_setter(32, 8, 2048)
+    rng = inputs.rng_for(5001)
+    lengths = [100, 1500, 3000, 7]
+    nxt, heads, offs = inputs.slab_lists(lengths, rng)
+    keys = rng.integers(0, 9, size=nxt.shape[0]).astype(np.uint32)
+    lo = int(offs[1])
+    order = [int(heads[1])]
+    while int(nxt[order[-1]]) != NIL:
+        order.append(int(nxt[order[-1]]))
+    cases = []
+    bad = nxt.copy(); bad[order[-1]] = order[500]                 # cycle
+    cases.append(bad)
+    bad = nxt.copy(); bad[order[10]] = int(offs[2]) + 3            # into the next slab
+    cases.append(bad)
+    bad = nxt.copy(); bad[order[700]] = NIL                        # list cut in two
+    cases.append(bad)
+    bad = nxt.copy(); bad[order[3]] = 0xFFFFFFF0                   # index out of range
+    cases.append(bad)
+    for bad in cases:
+        st, nh, got = gpu_sort_lists(heads, offs, bad, keys, 8)
+        assert st == -2
+        assert np.array_equal(got, np.full_like(bad, NIL))
