@@ -47,7 +47,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=1 << 24)
-    ap.add_argument("--K", type=int, default=8, help="pattern bits (4 or 8; 0 = library choice)")
+    ap.add_argument("--K", type=int, default=0,
+                    help="pattern bits (1, 2, 4 or 8; 0 = the library's tuned choice)")
     ap.add_argument("--M", type=int, default=32, choices=[32, 64], help="key bits")
     ap.add_argument("--dist", default="uniform", choices=["uniform", "zipf", "distinct8"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -168,7 +169,8 @@ def stage_table(lib, pools, counts):
 def run_plain(args, lib, torch, np, inputs, bytemodel, EventPool):
     dev = torch.device("cuda:0")
     n, K, M = args.n, args.K, args.M
-    Keff = K if K else 8
+    from paper_cs_0511020_amd import _lib
+    Keff = K if K else _lib.tune_lookup(0, M, n)[0]
     passes = M // Keff
     seed = {"uniform": 2001, "zipf": 2002, "distinct8": 2003}[args.dist]
     rng = inputs.rng_for(seed)
@@ -222,8 +224,8 @@ def run_plain(args, lib, torch, np, inputs, bytemodel, EventPool):
 
     # the other pattern width on the same input (K = 4 beside K = 8)
     other = None
-    if K in (4, 8) and not args.no_other_k:
-        K2 = 12 - K
+    if Keff in (4, 8) and not args.no_other_k:
+        K2 = 12 - Keff
         ws2_bytes = _lib.workspace_bytes(n, M, K2)
         ws2 = torch.empty(ws2_bytes, dtype=torch.uint8, device=dev)
         out2 = torch.empty_like(next_in)
@@ -354,6 +356,7 @@ def run_extras(args, lib, torch, np, inputs, bytemodel):
     from paper_cs_0511020_amd import _lib
     dev = torch.device("cuda:0")
     n, K = args.n, args.K
+    Kshow = K if K else _lib.tune_lookup(0, 32, n)[0]
     rng = inputs.rng_for(2301)
     nxt, head, order = inputs.random_list(n, rng)
     keys = inputs.float_keys(n, 32, rng, specials=False)
@@ -468,11 +471,11 @@ def run_extras(args, lib, torch, np, inputs, bytemodel):
     del ws, next_in
     return {
         "float32_keys": {"workload": "single list n=%d binary32 keys, log-uniform magnitudes of "
-                                     "both signs, 25%% repeats, K=%d" % (n, K),
+                                     "both signs, 25%% repeats, K=%d" % (n, Kshow),
                          "ms": round(sort_ms, 4), "Mnodes_per_s": round(n / (sort_ms * 1e-3) / 1e6, 1),
                          "correct": ok_sort},
         "records": {"workload": "single list n=%d stored as 16-byte records {next, u32 key, "
-                                "u64 payload}, links rewritten in place, K=%d" % (n, K),
+                                "u64 payload}, links rewritten in place, K=%d" % (n, Kshow),
                     "ms": round(aos_ms - copy_ms, 4),
                     "Mnodes_per_s": round(n / ((aos_ms - copy_ms) * 1e-3) / 1e6, 1),
                     "note": "time of a restore copy of the records subtracted",
@@ -557,7 +560,8 @@ def run_batched(args, lib, torch, np, inputs, EventPool):
     d = inputs.slab_lists_device(lengths, seed=4001, M=32, local_copy=compare)
     L = int(lengths.shape[0])
     total = int(d["offsets_host"][-1])
-    M, K = 32, 8
+    M, K = 32, 0  # the tuned pattern width and cutoff
+    Keff, cutoff = _lib.tune_lookup(1, M, total)
     ws_bytes = _lib.lists_workspace_bytes(total, L, M, K)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     next_out = torch.empty_like(d["next"])
@@ -651,7 +655,9 @@ def run_batched(args, lib, torch, np, inputs, EventPool):
 
     out = {
         "workload": "20000 lists, lengths log-uniform in [16, 2^%d], %d nodes, uint32 keys, "
-                    "random layout per slab, K=8" % (hi, total),
+                    "random layout per slab, K=%d (tuned), short-list cutoff %d (tuned)"
+                    % (hi, total, Keff, cutoff),
+        "K": Keff, "cutoff": cutoff,
         "oracle_sampled_lists": len(picks),
         "oracle_equal": oracle_ok,
         "lists": L, "nodes": total,

@@ -265,11 +265,9 @@ bool make_plan_lists(uint64_t n, uint32_t num_lists, uint32_t M, uint32_t K, uin
     P->cutoff = cutoff;
     P->seg_max = (uint32_t)seg_max;
     P->seg_chunks = (uint32_t)seg_chunks;
-    // a pack block's chunk meets at most chunk / (cutoff + 1) + 2 segments
-    uint64_t chunk = (uint64_t)(kPackSlots - 2) * (cutoff + 1);
-    if (chunk > 16384)
-        chunk = 16384;
-    P->pack_chunk = (uint32_t)(chunk & ~255ull);
+    // nodes per pack block: its digit counts flush once per block, so large
+    // chunks (whole steps of 4 waves x 256 nodes)
+    P->pack_chunk = 32768;
     P->o_table = off;
     off = align_up(off + (ceil_div(n, 1ull << P->log_block) + 1) * 4);
     P->o_headbits = off;  // cleared by its own launch at the start of every sort
@@ -453,7 +451,7 @@ extern "C" const char* pbit_stage_name(int stage)
 {
     static const char* names[] = {"zero", "pack", "walk0", "walk_up", "base", "down",
                                   "unchain", "schedule", "digit_pass", "relink", "plan",
-                                  "small_lists", "bases", "end"};
+                                  "small_lists", "bases", "commit", "end"};
     static_assert(sizeof(names) / sizeof(names[0]) == kStageCount + 1, "stage names");
     if (stage < 0 || stage > (int)kStageCount)
         return "unknown";

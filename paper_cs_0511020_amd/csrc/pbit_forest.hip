@@ -23,8 +23,9 @@
 //    own range: no pass on list ids is needed.  The per-list digit counts
 //    come from pack; the bases from a scan over lists (k_lprep, k_lscan,
 //    k_lfin).
-// The relink closes every list with NIL.  Every step is one launch over all
-// lists, and no results are written before the whole batch is validated.
+// The relink closes every segment with NIL and a commit step copies the short
+// lists' results out.  Every step is one launch over all lists, and no
+// results are written before the whole batch is validated.
 #include "pbit_device.h"
 #include "pbit_launch.h"
 
@@ -198,8 +199,9 @@ __device__ __forceinline__ bool forest_shape_ok(const Header* hdr)
 // Pack for the segments: records {next, transformed key} of segment nodes,
 // the in-degree hash sums and NIL count over them, and every segment's digit
 // counts for every pass.  A block takes a contiguous chunk of node indices;
-// the segments it meets (at most kPackSlots, by the plan's chunk size) count
-// in LDS, then flush once per (segment, pass, digit).  Nodes of short lists
+// the first kPackSlots segments it meets count in LDS and flush once per
+// (segment, pass, digit), any further ones (only when many lists just above
+// the cutoff share a chunk) count with global atomics.  Nodes of short lists
 // are left to k_fsmall.
 template <typename KeyT, int RB, class Src>
 __global__ __launch_bounds__(256) void k_fpack(Src src, ForestArgs F, uint32_t chunk,
@@ -221,14 +223,8 @@ __global__ __launch_bounds__(256) void k_fpack(Src src, ForestArgs F, uint32_t c
     bool bad = false;
     uint64_t h1 = 0, h2 = 0;
     uint32_t nils = 0;
-    for (uint64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
-        const uint32_t l = list_of(F.lm, (uint32_t)i);
-        const uint32_t s = F.lrank[l];
-        if (F.lrank[l + 1] == s)
-            continue;  // a short list's node
-        uint32_t nx;
-        KeyT k;
-        src.load(i, F.n, nx, k, bad);
+    // one segment node: key transform, hashes, NIL count, digit counts
+    auto count = [&](uint64_t i, uint32_t nx, KeyT k, uint32_t s) -> KeyT {
         k = transform_key<KeyT>(k, float_sel, xor_mask);
         if (nx == kNil) {
             nils++;
@@ -238,11 +234,6 @@ __global__ __launch_bounds__(256) void k_fpack(Src src, ForestArgs F, uint32_t c
         }
         h1 -= mix64(i + 1ull, kHashK1);
         h2 -= mix64(i + 1ull, kHashK2);
-        NodeRec<KeyT> r;
-        r.next = nx;
-        r.key = k;
-        if constexpr (sizeof(KeyT) == 8) r.pad = 0;
-        nodes[i] = r;
         const uint32_t slot = s - seg0;
         for (uint32_t p = 0; p < passes; p++) {
             const uint32_t d = (uint32_t)(k >> (p * RB)) & (RADIX - 1u);
@@ -250,6 +241,62 @@ __global__ __launch_bounds__(256) void k_fpack(Src src, ForestArgs F, uint32_t c
                 atomicAdd(&s_hist[slot * per_slot + p * RADIX + d], 1u);
             else
                 atomicAdd(&lcnt[((size_t)p * seg_max + s) * RADIX + d], 1u);
+        }
+        return k;
+    };
+    auto one = [&](uint64_t i, uint32_t s) {
+        uint32_t nx;
+        KeyT k;
+        src.load(i, F.n, nx, k, bad);
+        k = count(i, nx, k, s);
+        NodeRec<KeyT> r;
+        r.next = nx;
+        r.key = k;
+        if constexpr (sizeof(KeyT) == 8) r.pad = 0;
+        nodes[i] = r;
+    };
+    // Each wave takes 256 consecutive nodes at a time, 4 per lane.  Usually
+    // they all belong to one list: then the list is looked up once (and a
+    // short list's nodes are skipped without a read), and 32-bit keys move
+    // with 16-byte loads and 32-byte record stores.
+    bool wide = false;
+    if constexpr (Loads4<Src>::value)
+        wide = (((uintptr_t)src.next | (uintptr_t)src.keys) & 15u) == 0;
+    const uint32_t wave = threadIdx.x / 64, lane = __lane_id();
+    for (uint64_t g0 = c0 + (uint64_t)wave * 256; g0 < c1; g0 += blockDim.x * 4ull) {
+        const uint64_t g1 = min<uint64_t>(g0 + 256, c1);
+        const uint32_t la = list_of(F.lm, (uint32_t)g0), lb = list_of(F.lm, (uint32_t)(g1 - 1));
+        const uint64_t q0 = g0 + 4ull * lane;
+        if (la == lb) {
+            const uint32_t s = F.lrank[la];
+            if (F.lrank[la + 1] == s)
+                continue;  // a short list's nodes
+            if constexpr (Loads4<Src>::value) {
+                if (wide && q0 + 4 <= g1) {
+                    const uint4 a = ((const uint4*)src.next)[q0 / 4];
+                    const uint4 b = ((const uint4*)src.keys)[q0 / 4];
+                    const uint32_t nx[4] = {a.x, a.y, a.z, a.w};
+                    uint32_t k[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        bad |= (nx[j] != kNil) && (nx[j] >= F.n);
+                        k[j] = count(q0 + j, nx[j], k[j], s);
+                    }
+                    uint4* out = (uint4*)(nodes + q0);
+                    out[0] = make_uint4(nx[0], k[0], nx[1], k[1]);
+                    out[1] = make_uint4(nx[2], k[2], nx[3], k[3]);
+                    continue;
+                }
+            }
+            for (uint64_t i = q0; i < min<uint64_t>(q0 + 4, g1); i++)
+                one(i, s);
+        } else {
+            for (uint64_t i = q0; i < min<uint64_t>(q0 + 4, g1); i++) {
+                const uint32_t l = list_of(F.lm, (uint32_t)i);
+                const uint32_t s = F.lrank[l];
+                if (F.lrank[l + 1] != s)
+                    one(i, s);
+            }
         }
     }
     if (bad)
@@ -261,8 +308,7 @@ __global__ __launch_bounds__(256) void k_fpack(Src src, ForestArgs F, uint32_t c
     }
     __shared__ uint64_t s_h[2][4];
     __shared__ uint32_t s_nil[4];
-    const uint32_t wave = threadIdx.x / 64;
-    if (__lane_id() == 0) {
+    if (lane == 0) {
         s_h[0][wave] = h1;
         s_h[1][wave] = h2;
         s_nil[wave] = nils;
@@ -283,7 +329,10 @@ __global__ __launch_bounds__(256) void k_fpack(Src src, ForestArgs F, uint32_t c
         if (z)
             atomicAdd(&hdr->nil_count, z);
     }
-    for (uint32_t i = threadIdx.x; i < kPackSlots * per_slot; i += blockDim.x) {
+    // only the slots of segments this chunk met
+    const uint32_t used =
+        c0 < c1 ? min(kPackSlots, F.lrank[list_of(F.lm, (uint32_t)(c1 - 1)) + 1] - seg0) : 0u;
+    for (uint32_t i = threadIdx.x; i < used * per_slot; i += blockDim.x) {
         const uint32_t v = s_hist[i];
         if (v) {
             const uint32_t slot = i / per_slot, r = i % per_slot;
@@ -850,68 +899,78 @@ __global__ __launch_bounds__(256) void k_lfin(const uint32_t* __restrict__ lcnt,
 }
 
 // ---------------------------------------------------------------- relink
-// Thread j, once the batch is known to be valid:
-//  - position j of the segments: next_out[order[j]] = order[j+1] inside the
-//    segment's range, NIL at its end; its first node is the list's new head;
-//  - node j of a short list: its new link from snext;
-//  - list j: NIL as the head of an empty list, the head of a short list.
-// In the gather form results go to each list's own array in list-local
-// indices.
+// Thread j, once the batch is known to be valid, at position j of the
+// segments: next_out[order[j]] = order[j+1] inside the segment's range, NIL
+// at its end; the segment's first node is its list's new head.  In the
+// gather form results go to each list's own array in list-local indices.
 __global__ __launch_bounds__(256) void k_frelink(OrderSrc src, ForestArgs F,
                                                  const uint32_t* __restrict__ ctable,
-                                                 const uint32_t* __restrict__ snext,
+                                                 uint32_t* __restrict__ next_out,
+                                                 uint32_t* __restrict__ new_heads,
+                                                 const Header* hdr)
+{
+    if (hdr->status != 0)
+        return;
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= hdr->seg_nodes)
+        return;
+    const SegMap sm{ctable, F.coff, nullptr};
+    const uint32_t s = seg_of(sm, j, hdr->n_segs);
+    const uint32_t l = F.segl[s];
+    const uint32_t c1 = F.coff[s + 1];
+    const uint32_t kind = hdr->final_kind;
+    const uint32_t node = order_at(src, kind, j);
+    const uint32_t succ = (j + 1 < c1) ? order_at(src, kind, j + 1) : kNil;
+    const uint64_t lo = F.offsets[l], hi = F.offsets[l + 1];
+    if (node < lo || node >= hi)
+        return;  // cannot happen for a sorted batch; keeps every write in bounds
+    if (F.next_out_ptrs) {
+        ((uint32_t*)F.next_out_ptrs[l])[node - lo] = succ == kNil ? kNil : (uint32_t)(succ - lo);
+        if (j == F.coff[s])
+            new_heads[l] = (uint32_t)(node - lo);
+    } else {
+        next_out[node] = succ;
+        if (j == F.coff[s])
+            new_heads[l] = node;
+    }
+}
+
+// One workgroup per list, once the batch is known to be valid: a short
+// list's new links (sorted in LDS earlier) go to the caller's array in index
+// order and its new head to new_heads; an empty list gets NIL.  Thread 0 of
+// block 0 writes the batch status, valid or not.
+__global__ __launch_bounds__(256) void k_fcommit(ForestArgs F, const uint32_t* __restrict__ snext,
                                                  const uint32_t* __restrict__ shead,
                                                  uint32_t* __restrict__ next_out,
                                                  uint32_t* __restrict__ new_heads,
                                                  int32_t* __restrict__ d_status, const Header* hdr)
 {
     const int32_t st = hdr->status;
-    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j == 0)
+    const uint32_t l = blockIdx.x;
+    if (l == 0 && threadIdx.x == 0)
         *d_status = st;
-    if (st != 0)
+    if (st != 0 || l >= F.H || is_seg(F, l))
         return;
-    const bool gather = F.next_out_ptrs != nullptr;
-    if (j < F.H) {
-        const uint64_t lo = F.offsets[j], hi = F.offsets[j + 1];
-        if (hi == lo)
-            new_heads[j] = kNil;
-        else if (!is_seg(F, j))
-            new_heads[j] = shead[j] + (gather ? 0u : (uint32_t)lo);
+    const uint64_t lo = F.offsets[l], hi = F.offsets[l + 1];
+    if (hi == lo) {
+        if (threadIdx.x == 0)
+            new_heads[l] = kNil;
+        return;
     }
-    if (j < F.n) {
-        const uint32_t l = list_of(F.lm, j);
-        if (!is_seg(F, l)) {
-            const uint64_t lo = F.offsets[l];
-            const uint32_t v = snext[j];
-            if (gather)
-                ((uint32_t*)F.next_out_ptrs[l])[j - lo] = v;
-            else
-                next_out[j] = v == kNil ? kNil : v + (uint32_t)lo;
+    const uint32_t len = (uint32_t)(hi - lo);
+    if (F.next_out_ptrs) {
+        uint32_t* out = (uint32_t*)F.next_out_ptrs[l];
+        for (uint32_t i = threadIdx.x; i < len; i += blockDim.x)
+            out[i] = snext[lo + i];
+        if (threadIdx.x == 0)
+            new_heads[l] = shead[l];
+    } else {
+        for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
+            const uint32_t v = snext[lo + i];
+            next_out[lo + i] = v == kNil ? kNil : v + (uint32_t)lo;
         }
-    }
-    const uint32_t nseg = hdr->n_segs;
-    if (j < hdr->seg_nodes) {
-        const SegMap sm{ctable, F.coff, nullptr};
-        const uint32_t s = seg_of(sm, j, nseg);
-        const uint32_t l = F.segl[s];
-        const uint32_t c1 = F.coff[s + 1];
-        const uint32_t kind = hdr->final_kind;
-        const uint32_t node = order_at(src, kind, j);
-        const uint32_t succ = (j + 1 < c1) ? order_at(src, kind, j + 1) : kNil;
-        const uint64_t lo = F.offsets[l], hi = F.offsets[l + 1];
-        if (node < lo || node >= hi)
-            return;  // cannot happen for a sorted batch; keeps every write in bounds
-        if (gather) {
-            ((uint32_t*)F.next_out_ptrs[l])[node - lo] =
-                succ == kNil ? kNil : (uint32_t)(succ - lo);
-            if (j == F.coff[s])
-                new_heads[l] = (uint32_t)(node - lo);
-        } else {
-            next_out[node] = succ;
-            if (j == F.coff[s])
-                new_heads[l] = node;
-        }
+        if (threadIdx.x == 0)
+            new_heads[l] = shead[l] + (uint32_t)lo;
     }
 }
 
@@ -1125,11 +1184,15 @@ hipError_t enqueue_sort_lists(const Plan& P, const uint32_t* heads, const uint64
     if (e != hipSuccess)
         return e;
     {
-        const uint64_t threads = P.n > P.num_lists ? P.n : P.num_lists;
         mark(prof, s, kStageRelink);
         const OrderSrc src = P.key_bytes == 8 ? order_src<uint64_t>(P, ws) : order_src<uint32_t>(P, ws);
-        hipLaunchKernelGGL(k_frelink, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s,
-                           src, F, (const uint32_t*)(ws + P.o_ctable),
+        hipLaunchKernelGGL(k_frelink, dim3((uint32_t)((P.n + 255) / 256)), dim3(256), 0, s, src, F,
+                           (const uint32_t*)(ws + P.o_ctable), next_out, new_heads,
+                           (const Header*)hdr);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+        mark(prof, s, kStageCommit);
+        hipLaunchKernelGGL(k_fcommit, dim3(P.num_lists), dim3(256), 0, s, F,
                            (const uint32_t*)(ws + P.o_snext), (const uint32_t*)(ws + P.o_shead),
                            next_out, new_heads, d_status, (const Header*)hdr);
         if ((e = hipGetLastError()) != hipSuccess)

@@ -96,6 +96,7 @@ enum Stage : int32_t {
     kStagePlan,   // many-list sorts: slab checks, segments, tables
     kStageSmall,  // many-list sorts: short lists sorted in LDS
     kStageBases,  // many-list sorts: per-list digit bases
+    kStageCommit, // many-list sorts: short lists' results copied out
     kStageCount
 };
 
