@@ -256,6 +256,7 @@ uint32_t pbit_set_lookback_spin_limit(uint32_t sleeps);
  *   pbit_tune_set     adds or replaces the entry (kind, M, n_max); returns
  *                     PBIT_OK, PBIT_EINVAL (kind > 1, K not in {1,2,4,8} or
  *                     not dividing M, bad cutoff) or PBIT_ENOMEM (table full)
+ *   pbit_tune_clear   empties the table (the defaults above apply)
  *   pbit_tune_reset   restores the built-in table
  *   pbit_tune_lookup  the K and cutoff a sort of that kind, M and size gets
  * Workspace sizes depend on K only, never on the cutoff; a change of the
@@ -263,6 +264,7 @@ uint32_t pbit_set_lookback_spin_limit(uint32_t sleeps);
  * K and so make the workspace too small (PBIT_ENOMEM).
  */
 int pbit_tune_set(uint32_t kind, uint32_t M, uint64_t n_max, uint32_t K, uint32_t cutoff);
+void pbit_tune_clear(void);
 void pbit_tune_reset(void);
 int pbit_tune_lookup(uint32_t kind, uint32_t M, uint64_t n, uint32_t *K, uint32_t *cutoff);
 

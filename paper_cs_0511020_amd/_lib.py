@@ -58,6 +58,7 @@ _SIGNATURES = {
     "pbit_set_lookback_spin_limit": (ctypes.c_uint32, [ctypes.c_uint32]),
     "pbit_tune_set": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
                                      ctypes.c_uint32, ctypes.c_uint32]),
+    "pbit_tune_clear": (None, []),
     "pbit_tune_reset": (None, []),
     "pbit_tune_lookup": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
                                         ctypes.POINTER(ctypes.c_uint32),
@@ -100,7 +101,13 @@ def tune_set(kind: int, M: int, n_max: int, K: int, cutoff: int) -> int:
 
 
 def tune_reset() -> None:
+    """Back to the built-in table."""
     load().pbit_tune_reset()
+
+
+def tune_clear() -> None:
+    """An empty table: K = 8 (4 for M = 8) and cutoff 2048 everywhere."""
+    load().pbit_tune_clear()
 
 
 def tune_lookup(kind: int, M: int, n: int):

@@ -611,6 +611,12 @@ extern "C" int pbit_tune_set(uint32_t kind, uint32_t M, uint64_t n_max, uint32_t
     return PBIT_OK;
 }
 
+extern "C" void pbit_tune_clear(void)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_ntune = 0;
+}
+
 extern "C" void pbit_tune_reset(void)
 {
     std::lock_guard<std::mutex> lock(g_tune_mu);

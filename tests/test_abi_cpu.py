@@ -187,6 +187,9 @@ def test_tuning_table_is_read_and_applied(lib):
         assert _lib.tune_set(0, 32, 1, 3, 2048) == _lib.EINVAL
         assert _lib.tune_set(0, 8, 1, 16, 2048) == _lib.EINVAL
         assert _lib.tune_set(1, 32, 1, 8, 512) == _lib.EINVAL
+        _lib.tune_clear()
+        assert _lib.tune_lookup(1, 32, 5000) == (8, 2048)
+        assert _lib.tune_lookup(0, 8, 5000) == (4, 2048)
         _lib.tune_reset()
         assert _lib.tune_lookup(0, 32, 1 << 20) == (k0, c0)
         assert _lib.tune_lookup(1, 16, 5000) == (kb, cb)

@@ -260,6 +260,7 @@ def cutoff_setter():
     from paper_cs_0511020_amd import _lib
 
     def set_cutoff(M, K, cutoff):
+        _lib.tune_clear()  # no entry of the built-in table may win over this one
         assert _lib.tune_set(1, M, 0xFFFFFFFF, K, cutoff) == 0
         assert _lib.tune_lookup(1, M, 1000) == (K, cutoff)
     yield set_cutoff
