@@ -99,6 +99,27 @@ int pbit_sort_list_async(uint32_t head, const uint32_t *next_in, uint32_t *next_
                          void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the sort of
+ * pbit_sort_list_async with the workspace taken from a fixed array of
+ * PBIT_NOALLOC_SCRATCH_BYTES in each device's memory, which the library holds
+ * from its first such call on that device until the process ends.  Arguments,
+ * result and errors are those of pbit_sort_list_async without ws/ws_bytes;
+ * lists whose pbit_workspace_bytes(n, M, K) exceeds the array (about 700 000
+ * nodes with 32-bit keys, 380 000 with 64-bit keys) are refused with
+ * PBIT_ENOMEM and nothing queued.  The array belongs to the device current at
+ * the call, which must be the stream's device.  Nothing is allocated, freed
+ * or cleared with a memset: the sort's first kernel zeroes what must start at
+ * zero.  All calls on one device share its array: calls whose work may
+ * overlap on the device (other streams, or a graph replayed while another
+ * runs) race and must be serialised by the caller.
+ */
+#define PBIT_NOALLOC_SCRATCH_BYTES (64u << 20)
+int pbit_sort_list_noalloc(uint32_t head, const uint32_t *next_in, uint32_t *next_out,
+                           const void *keys, uint64_t n, uint32_t M, uint32_t K,
+                           uint32_t flags, uint32_t *d_result, void *stream);
+
+/*
  * Synchronous, in-place convenience form on the default stream: relinks
  * next[] and returns the new head (PBIT_NIL for an empty list) or a negative
  * status.  Uses a workspace the library keeps between calls (one per device,

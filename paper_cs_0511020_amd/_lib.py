@@ -24,6 +24,9 @@ _SIGNATURES = {
         ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
         ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
         ctypes.c_size_t, ctypes.c_void_p]),
+    "pbit_sort_list_noalloc": (ctypes.c_int, [
+        ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+        ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]),
     "pbit_sort_list": (ctypes.c_int64, [
         ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
         ctypes.c_uint32]),
@@ -148,6 +151,18 @@ def sort_list_async(head: int, next_in, next_out, keys, n: int, M: int, K: int, 
     return int(load().pbit_sort_list_async(
         int(head) & 0xFFFFFFFF, _ptr(next_in), _ptr(next_out), _ptr(keys), int(n), int(M),
         int(K), int(flags), _ptr(result), _ptr(ws), int(ws_bytes), _stream_handle(stream)))
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def sort_list_noalloc(head: int, next_in, next_out, keys, n: int, M: int, K: int, flags: int,
+                      result, stream=None) -> int:
+    """Raw C-ABI call of the form that allocates nothing (a fixed per-device
+    workspace of NOALLOC_SCRATCH_BYTES; concurrent calls on one device race)."""
+    return int(load().pbit_sort_list_noalloc(
+        int(head) & 0xFFFFFFFF, _ptr(next_in), _ptr(next_out), _ptr(keys), int(n), int(M),
+        int(K), int(flags), _ptr(result), _stream_handle(stream)))
 
 
 def lists_workspace_bytes(total: int, num_lists: int, M: int, K: int = 0) -> int:

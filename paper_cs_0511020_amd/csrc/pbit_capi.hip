@@ -372,6 +372,59 @@ extern "C" int pbit_sort_list_async(uint32_t head, const uint32_t* next_in, uint
                                 ws_bytes, stream, nullptr);
 }
 
+// ---------------------------------------------------------------- no allocation
+// Workspace of pbit_sort_list_noalloc: one array in every device's memory for
+// the life of the process.  Host code never passes `scratch` itself to a
+// kernel (on the host it names a stand-in, not device memory): the device
+// address of each device's copy is looked up once per device and kept.
+static __device__ __align__(256) unsigned char scratch[PBIT_NOALLOC_SCRATCH_BYTES];
+
+struct ScratchSlot {
+    std::once_flag once;
+    void* ptr = nullptr;
+    hipError_t err = hipSuccess;
+};
+
+static ScratchSlot& scratch_slot(int dev)
+{
+    static ScratchSlot slots[64];
+    return slots[dev & 63];
+}
+
+// Device address of the current device's scratch array (nullptr on failure).
+static void* scratch_ptr()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return nullptr;
+    ScratchSlot& sl = scratch_slot(dev);
+    std::call_once(sl.once, [&sl]() {
+        void* p = nullptr;
+        sl.err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        sl.ptr = sl.err == hipSuccess ? p : nullptr;
+    });
+    return sl.ptr;
+}
+
+extern "C" int pbit_sort_list_noalloc(uint32_t head, const uint32_t* next_in, uint32_t* next_out,
+                                      const void* keys, uint64_t n, uint32_t M, uint32_t K,
+                                      uint32_t flags, uint32_t* d_result, void* stream)
+{
+    Plan P;
+    if (!make_plan(n, M, K, flags, &P))
+        return PBIT_EINVAL;
+    if (P.total > (size_t)PBIT_NOALLOC_SCRATCH_BYTES)
+        return PBIT_ENOMEM;  // the list needs more workspace than the fixed array holds
+    void* ws = scratch_ptr();
+    if (!ws)
+        return PBIT_EHIP;
+    // the same kernels as pbit_sort_list_async, on the fixed array; every
+    // region that must start at zero is cleared by the sort's own first
+    // kernel, so nothing left by an earlier call matters
+    return sort_list_async_impl(head, next_in, next_out, keys, n, M, K, flags, d_result, ws,
+                                (size_t)PBIT_NOALLOC_SCRATCH_BYTES, stream, nullptr);
+}
+
 extern "C" int pbit_sort_list_profiled(uint32_t head, const uint32_t* next_in,
                                        uint32_t* next_out, const void* keys, uint64_t n,
                                        uint32_t M, uint32_t K, uint32_t flags,
