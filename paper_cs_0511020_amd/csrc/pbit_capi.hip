@@ -38,7 +38,10 @@ static size_t entry_bytes(uint32_t key_bytes) { return key_bytes == 8 ? 16 : 8; 
 static size_t node_bytes(uint32_t key_bytes) { return key_bytes == 8 ? 16 : 8; }
 static size_t pair_bytes(uint32_t key_bytes) { return key_bytes == 8 ? 12 : 8; }
 // Entries a level-0 walker gathers in registers per burst (the device SegLen).
-static uint32_t reg_entries(uint32_t key_bytes) { return key_bytes == 8 ? 16 : 32; }
+static uint32_t reg_entries(uint32_t key_bytes)
+{
+    return key_bytes == 8 ? PBIT_SEGLEN / 2 : PBIT_SEGLEN;
+}
 
 // Entries stored per level-0 chain (a multiple of the walker's register
 // block).  Chain lengths are geometric with mean 16, so a slot of 128 leaves

@@ -79,7 +79,9 @@ __device__ __forceinline__ uint32_t order_at(const OrderSrc& o, uint32_t kind, u
 }
 
 // Entries of a level-0 chain a walker gathers in registers before storing them.
-template <typename KeyT> struct SegLen { static constexpr uint32_t value = sizeof(KeyT) == 8 ? 16 : 32; };
+template <typename KeyT> struct SegLen {
+    static constexpr uint32_t value = sizeof(KeyT) == 8 ? PBIT_SEGLEN / 2 : PBIT_SEGLEN;
+};
 
 // Digit-pass tile shape (block threads x items per thread), the same for
 // every pattern width.  The pass is latency-bound, so the shape is chosen for

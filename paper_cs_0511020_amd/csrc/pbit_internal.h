@@ -18,6 +18,11 @@ constexpr uint32_t kNil = 0xFFFFFFFFu;
 #ifndef PBIT_BASEMAX
 #define PBIT_BASEMAX 8192
 #endif
+// Level-0 entries a walker keeps in registers between stores (half for
+// 64-bit keys); the chain slots hold a multiple of it.
+#ifndef PBIT_SEGLEN
+#define PBIT_SEGLEN 32
+#endif
 constexpr uint32_t kLog0 = PBIT_LOG0;
 // Levels >= 1 walk the list of chains of the level below.
 constexpr uint32_t kLogUp = PBIT_LOGUP;
