@@ -54,12 +54,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=1 << 24,
                     help="nodes in the list the CPU oracle sorts once")
-    ap.add_argument("--batched", default="short", choices=["none", "short", "long"],
+    ap.add_argument("--batched", default="long", choices=["none", "short", "long"],
                     help="batched section: 20 000 lists of 16..2^16 nodes (short) or 16..2^20 (long)")
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--no-plain-compare", action="store_true",
                     help="skip the 20 000 single-list calls of the batched comparison")
-    ap.add_argument("--served", default="small", choices=["none", "small", "full"],
+    ap.add_argument("--served", default="full", choices=["none", "small", "full"],
                     help="served section: 300 requests up to 2^20 nodes (small) or 2000 up "
                          "to 2^24 (full)")
     ap.add_argument("--no-cold", action="store_true",

@@ -29,6 +29,13 @@
  * 2008, Sec. 5.10).  PBIT_SIGNED and PBIT_FLOAT together are PBIT_EINVAL.
  * Equal keys (equal bit patterns) keep list order in every mode.
  *
+ * PBIT_SHARED changes no result, only how the digit passes hand out their
+ * tiles: by default neighbouring tiles go to one XCD in chunks (their writes
+ * merge in that XCD's L2), which assumes the sort has the device to itself;
+ * with PBIT_SHARED tiles are claimed in the order blocks start, which stays
+ * fast when other kernels (other sorts on other streams) hold parts of the
+ * device, at about 10 % more digit-pass time when they do not.
+ *
  * Errors are negative return values:
  *   PBIT_EINVAL     bad argument found on the host (no device work queued):
  *                   M not in {8,16,32,64}, K not in {0,1,2,4,8} or not
@@ -69,7 +76,8 @@ enum {
     PBIT_ASCENDING = 0,
     PBIT_DESCENDING = 1, /* Sec. 6: largest key first                 */
     PBIT_SIGNED = 2,     /* Sec. 7-8: two's-complement keys           */
-    PBIT_FLOAT = 4       /* Sec. 14: IEEE-754 sign-magnitude keys     */
+    PBIT_FLOAT = 4,      /* Sec. 14: IEEE-754 sign-magnitude keys     */
+    PBIT_SHARED = 8      /* other kernels may run on the device at the same time */
 };
 
 /*

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libpbit.so")
 NIL = 0xFFFFFFFF
 MAX_NODES = (1 << 32) - 2
 OK, EINVAL, EMALFORMED, ENOMEM, EHIP = 0, -1, -2, -3, -4
-ASCENDING, DESCENDING, SIGNED, FLOAT = 0, 1, 2, 4
+ASCENDING, DESCENDING, SIGNED, FLOAT, SHARED = 0, 1, 2, 4, 8
 
 # name -> (restype, argtypes)
 _SIGNATURES = {

@@ -126,7 +126,8 @@ static bool plan_common(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, size
                         uint64_t level0_chains, uint32_t cap, size_t lcnt_bytes, Plan* P,
                         size_t& off)
 {
-    if (!valid_k(M, K) || (flags & ~(uint32_t)(PBIT_DESCENDING | PBIT_SIGNED | PBIT_FLOAT)) != 0 ||
+    if (!valid_k(M, K) ||
+        (flags & ~(uint32_t)(PBIT_DESCENDING | PBIT_SIGNED | PBIT_FLOAT | PBIT_SHARED)) != 0 ||
         ((flags & PBIT_SIGNED) && (flags & PBIT_FLOAT)))
         return false;
     P->n = n;

@@ -100,16 +100,19 @@ template <typename KeyT, int RB> struct PassShape {
     static constexpr int items = sizeof(KeyT) == 8 ? 8 : 6;
     static constexpr int waves = sizeof(KeyT) == 8 ? 4 : 8;
 };
-// Consecutive tiles given to one XCD in a row.  Work-groups go to the 8 XCDs
-// round-robin by block index, so block b takes tile
-//   (q / C) * 8C + (b % 8) * C + q % C,  q = b / 8, C = kPassChunk:
-// each XCD then writes C neighbouring tiles' runs of every digit, and the
-// partial cache lines where two tiles' runs meet merge in that XCD's L2
-// instead of being written back twice.  The look-back still follows tile
-// order; the tile a chunk's first tile waits on starts 8(C-1) blocks later,
-// so a group of 8C blocks must fit on the chip at once: 128 blocks, against
-// 256 resident 64-bit-key blocks and 512 or more of the others.  (8, 16 and
-// 32 were measured; 16 was fastest or tied everywhere.)
+
+// Consecutive tiles given to one XCD in a row (default tile order).
+// Work-groups go to the 8 XCDs round-robin by block index, so block b takes
+// tile (q / C) * 8C + (b % 8) * C + q % C, q = b / 8, C = kPassChunk: each
+// XCD then writes C neighbouring tiles' runs of every digit, and the partial
+// cache lines where two tiles' runs meet merge in that XCD's L2 instead of
+// being written back twice (with 8-bit patterns a tile's runs average 24
+// elements, so most of its writes touch such lines: 11 % of the pass time at
+// 2^24 keys).  The look-back follows tile order, so the first tile of a chunk
+// waits on a tile that starts 8(C-1) blocks later.  When other kernels share
+// the device they can hold the XCDs such a tile needs; calls that expect that
+// take tiles from a ticket counter in block start order instead (PBIT_SHARED),
+// which never waits on a tile that has not started.
 constexpr uint32_t kPassChunk = 16;
 
 __device__ __forceinline__ void set_error(int32_t* status, int32_t code)
@@ -588,8 +591,7 @@ constexpr uint32_t kTileSegs = 16;
 
 // ---------------------------------------------------------------- digit pass
 // One stable split on the pattern at bit `shift`.  A tile of BLOCK * ITEMS
-// consecutive list positions (block -> tile in XCD chunks, see kPassChunk) is
-// loaded wave-striped and ranked per wave: an item's peers (the lanes whose
+// consecutive list positions is loaded wave-striped and ranked per wave: an item's peers (the lanes whose
 // item has the same digit) come from a per-wave LDS lane mask per digit (or,
 // when one digit is frequent enough to make lanes queue on one mask word,
 // from K ballots, as the schedule decides per pass); the
@@ -597,9 +599,10 @@ constexpr uint32_t kTileSegs = 16;
 // counter (items in program order) and its peers take the returned base from
 // it.  Counts are scanned across waves, tiles are chained by decoupled
 // look-back (Merrill & Garland), and the tile is staged in LDS grouped by
-// digit and written out in runs.  The look-back spin is bounded: a tile that
-// waits too long on a predecessor counts that predecessor's digit in its
-// input itself, so no tile ever waits on a tile that has not been scheduled.
+// digit and written out in runs.  Tiles go to blocks in XCD chunks (see
+// kPassChunk) or, with `ticket`, in block start order from a per-pass
+// counter.  The look-back spin is bounded: a tile that waits too long on a
+// predecessor counts that predecessor's digit in its input itself.
 //
 // An element's destination is base + P_d(j), where P_d(j) is the number of
 // elements before position j with the same digit d (local rank plus the
@@ -629,7 +632,7 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
     uint32_t pass, uint32_t shift, uint32_t n_all, Pair<KeyT>* __restrict__ pairsA,
     Pair<KeyT>* __restrict__ pairsB, uint32_t* __restrict__ idxA, uint32_t* __restrict__ idxB,
     const uint32_t* __restrict__ dbase, LW* __restrict__ look, Header* hdr, SegMap sm,
-    uint32_t spin_limit)
+    uint32_t spin_limit, uint32_t ticket)
 {
     using LK = Look<LW>;
     constexpr uint32_t RADIX = 1u << RB;
@@ -664,15 +667,20 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
 
     const uint32_t tid = threadIdx.x;
     const uint32_t wave = tid / 64, lane = tid % 64;
+    __shared__ uint32_t s_tile;
+    if (ticket && tid == 0)
+        s_tile = atomicAdd(&hdr->pass_ticket[pass], 1u);
     for (uint32_t i = tid; i < WAVES * RADIX; i += BLOCK) {
         (&s_wave[0][0])[i] = 0;
         s_mask[i] = 0ull;
     }
+    __syncthreads();
     const uint32_t q = blockIdx.x / 8u;
-    const uint32_t tile = (q / kPassChunk) * (8u * kPassChunk) + (blockIdx.x % 8u) * kPassChunk +
-                          q % kPassChunk;
+    const uint32_t tile = ticket ? s_tile
+                                 : (q / kPassChunk) * (8u * kPassChunk) +
+                                       (blockIdx.x % 8u) * kPassChunk + q % kPassChunk;
     if ((uint64_t)tile * TILE >= (uint64_t)n)
-        return;  // the grid is rounded up to whole chunk groups (and, SEG, to all nodes)
+        return;  // the grid is rounded up to whole chunk groups (SEG: to all nodes)
     const uint64_t tbase = (uint64_t)tile * TILE;
     const uint64_t wbase = tbase + (uint64_t)wave * (64 * ITEMS);
     uint32_t seg0 = 0, nb = 0;
@@ -686,8 +694,8 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
         }
         for (uint32_t k = 0; k < kTileSegs; k++)
             nb += (seg0 + 1 + k < nseg) && (sm.coff[seg0 + 1 + k] < tend);
+        __syncthreads();
     }
-    __syncthreads();
 
     KeyT key[ITEMS];
     uint32_t idx[ITEMS], dig[ITEMS], rank[ITEMS];

@@ -79,6 +79,7 @@ struct Header {
     uint32_t seg_nodes;       // many-list sorts: their nodes
     uint32_t pad1;
     uint32_t seg_trivial[kMaxPasses];  // lists whose pattern p is one value for all nodes
+    uint32_t pass_ticket[kMaxPasses];  // next tile of each digit pass, in block start order
     PassSched sched[kMaxPasses];
 };
 

@@ -94,8 +94,9 @@ static hipError_t launch_passes_rb(const Plan& P, char* ws, hipStream_t s, Prof*
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }
+    const uint32_t ticket = (P.flags & PBIT_SHARED) ? 1u : 0u;
     const uint32_t group = 8u * kPassChunk;
-    const uint32_t grid = (uint32_t)((P.tiles + group - 1) / group * group);
+    const uint32_t grid = ticket ? P.tiles : (uint32_t)((P.tiles + group - 1) / group * group);
     for (uint32_t p = 0; p < P.passes; p++) {
         LW* look = (LW*)(ws + P.o_look) + (size_t)p * P.tiles * RADIX;
         const uint32_t* dbase = SEG ? nullptr : (const uint32_t*)(ws + P.o_dbase) + (size_t)p * RADIX;
@@ -108,7 +109,7 @@ static hipError_t launch_passes_rb(const Plan& P, char* ws, hipStream_t s, Prof*
                            dim3(BLOCK), 0, s, p, p * RB, (uint32_t)P.n,
                            (Pair<KeyT>*)(ws + P.o_pairsA), (Pair<KeyT>*)(ws + P.o_pairsB),
                            (uint32_t*)(ws + P.o_idxA), (uint32_t*)(ws + P.o_idxB), dbase, look,
-                           (Header*)(ws + P.o_header), sm, P.spin_limit);
+                           (Header*)(ws + P.o_header), sm, P.spin_limit, ticket);
         e = hipGetLastError();
         if (e != hipSuccess)
             return e;

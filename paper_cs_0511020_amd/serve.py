@@ -69,6 +69,8 @@ class GpuExecutor:
         self.device = torch.device(device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
         self.K = K
+        # sorts on several streams run at the same time: tiles in start order
+        self.flags = _lib.SHARED if streams > 1 else 0
         self.next_stream = 0
         self.t0_event = None
         self.lib = _lib.load()
@@ -105,7 +107,8 @@ class GpuExecutor:
             status = torch.zeros(1, dtype=torch.int32, device=self.device)
             st = self.lib.pbit_sort_lists_gather(
                 d_heads.data_ptr(), d_offs.data_ptr(), L, total, d_meta[1].data_ptr(),
-                d_meta[2].data_ptr(), d_meta[3].data_ptr(), M, self.K, 0, new_heads.data_ptr(),
+                d_meta[2].data_ptr(), d_meta[3].data_ptr(), M, self.K, self.flags,
+                new_heads.data_ptr(),
                 status.data_ptr(), ws.data_ptr(), wsb, int(stream.cuda_stream))
             if st != 0:
                 raise RuntimeError("batched launch failed: " + _lib.status_string(st))
@@ -126,7 +129,7 @@ class GpuExecutor:
             ws = torch.empty(wsb, dtype=torch.uint8, device=self.device)
             res = torch.zeros(2, dtype=torch.int32, device=self.device)
             st = self.lib.pbit_sort_list_async(r.head, r.next.data_ptr(), r.out.data_ptr(),
-                                               r.keys.data_ptr(), r.n, r.M, self.K, 0,
+                                               r.keys.data_ptr(), r.n, r.M, self.K, self.flags,
                                                res.data_ptr(), ws.data_ptr(), wsb,
                                                int(stream.cuda_stream))
             if st != 0:

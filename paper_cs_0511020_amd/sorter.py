@@ -23,9 +23,12 @@ def key_bits(keys: torch.Tensor) -> int:
         raise TypeError("unsupported key dtype %s" % keys.dtype) from None
 
 
-def key_flags(keys: torch.Tensor, descending: bool, signed: bool) -> int:
-    """Flag word for a key tensor: floating-point dtypes sort by value."""
+def key_flags(keys: torch.Tensor, descending: bool, signed: bool, shared: bool = False) -> int:
+    """Flag word for a key tensor: floating-point dtypes sort by value;
+    ``shared``: other sorts may run on the device at the same time."""
     flags = _lib.DESCENDING if descending else 0
+    if shared:
+        flags |= _lib.SHARED
     if keys.is_floating_point():
         if signed:
             raise ValueError("signed applies to integer keys only")
@@ -96,7 +99,8 @@ class ListSorter:
     def sort_async(self, head: int, next_in: torch.Tensor, keys: torch.Tensor, K: int = 0,
                    descending: bool = False, signed: bool = False,
                    next_out: torch.Tensor | None = None, result: torch.Tensor | None = None,
-                   stream=None, prev_out: torch.Tensor | None = None) -> torch.Tensor:
+                   stream=None, prev_out: torch.Tensor | None = None,
+                   shared: bool = False) -> torch.Tensor:
         """Queue the sort; returns the 2-word device result {head, status}.
 
         With ``prev_out`` (n uint32 entries, not the next array) the list is
@@ -112,7 +116,7 @@ class ListSorter:
             result = self.result
         ws = self.workspace(n, M, K)
         _note_stream(self._ws_streams, stream, result)
-        flags = key_flags(keys, descending, signed)
+        flags = key_flags(keys, descending, signed, shared)
         st = _lib.sort_list_async(head, next_in, next_out, keys, n, M, K, flags, result, ws,
                                   self._ws_bytes, stream)
         if st == _lib.OK and prev_out is not None:
@@ -192,7 +196,7 @@ class ListsSorter:
 
     def sort_async(self, heads, offsets, next_in, keys, K: int = 0, descending: bool = False,
                    signed: bool = False, next_out=None, new_heads=None, status=None,
-                   stream=None, prev_out=None):
+                   stream=None, prev_out=None, shared: bool = False):
         L = int(heads.numel())
         total = int(next_in.numel())
         M = key_bits(keys)
@@ -204,7 +208,7 @@ class ListsSorter:
             status = self.status
         ws = self.workspace(total, L, M, K)
         _note_stream(self._ws_streams, stream, new_heads, status)
-        flags = key_flags(keys, descending, signed)
+        flags = key_flags(keys, descending, signed, shared)
         st = _lib.sort_lists(heads, offsets, L, total, next_in, next_out, keys, M, K, flags,
                              new_heads, status, ws, self._ws_bytes, stream)
         if st == _lib.OK and prev_out is not None:

@@ -33,7 +33,7 @@ def keys_to_dev(keys, flags, torch):
     return to_dev(keys, torch)
 
 
-def gpu_sort(head, nxt, keys, K, flags=0, inplace=True, sorter=None):
+def gpu_sort(head, nxt, keys, K, flags=0, inplace=True, sorter=None, shared=False):
     import torch
     from paper_cs_0511020_amd.sorter import ListSorter
     sorter = sorter or ListSorter()
@@ -41,7 +41,7 @@ def gpu_sort(head, nxt, keys, K, flags=0, inplace=True, sorter=None):
     kt = keys_to_dev(keys, flags, torch)
     out = None if inplace else torch.full_like(nt, -1)
     res = sorter.sort_async(head, nt, kt, K, descending=bool(flags & 1),
-                            signed=bool(flags & 2), next_out=out)
+                            signed=bool(flags & 2), next_out=out, shared=shared)
     torch.cuda.synchronize()
     h, st = (int(x) & 0xFFFFFFFF for x in res.cpu().tolist())
     st = st - (1 << 32) if st >> 31 else st

@@ -88,7 +88,7 @@ def test_host_argument_checks(lib):
     assert _call(lib, M=12) == E
     assert _call(lib, K=3) == E
     assert _call(lib, M=8, K=16) == E
-    assert _call(lib, flags=8) == E
+    assert _call(lib, flags=16) == E         # unknown flag bit
     assert _call(lib, flags=_lib.SIGNED | _lib.FLOAT) == E
     assert _call(lib, res=0) == E
     assert _call(lib, res=0x2002) == E            # misaligned result
@@ -158,7 +158,7 @@ def test_lists_host_checks(lib):
     assert call(offs=0x2004) == E      # offsets must be 8-byte aligned
     assert call(st=0) == E
     assert call(nin=0) == E
-    assert call(flags=8) == E
+    assert call(flags=16) == E
     assert call(flags=_lib.SIGNED | _lib.FLOAT) == E
     assert call(wsb=100) == _lib.ENOMEM
 

@@ -24,7 +24,7 @@ def _gpu():
     _lib.load()
 
 
-def gpu_sort_lists(heads, offsets, nxt, keys, K, flags=0, inplace=False):
+def gpu_sort_lists(heads, offsets, nxt, keys, K, flags=0, inplace=False, shared=False):
     import torch
     from paper_cs_0511020_amd.sorter import ListsSorter
     s = ListsSorter()
@@ -34,7 +34,7 @@ def gpu_sort_lists(heads, offsets, nxt, keys, K, flags=0, inplace=False):
     kt = keys_to_dev(keys, flags, torch)
     out = None if inplace else torch.full_like(nt, -1)
     new_heads, status = s.sort_async(ht, ot, nt, kt, K, descending=bool(flags & 1),
-                                     signed=bool(flags & 2), next_out=out)
+                                     signed=bool(flags & 2), next_out=out, shared=shared)
     torch.cuda.synchronize()
     st = int(status.item())
     got = (nt if inplace else out).cpu().numpy().view(np.uint32)
@@ -49,8 +49,8 @@ def oracle_lists(oracle_mod, heads, offsets, nxt, keys, K, flags=0):
     return nh, out
 
 
-def check(oracle_mod, heads, offsets, nxt, keys, K, flags=0, inplace=False):
-    st, nh, got = gpu_sort_lists(heads, offsets, nxt, keys, K, flags, inplace)
+def check(oracle_mod, heads, offsets, nxt, keys, K, flags=0, inplace=False, shared=False):
+    st, nh, got = gpu_sort_lists(heads, offsets, nxt, keys, K, flags, inplace, shared)
     assert st == 0
     enh, enext = oracle_lists(oracle_mod, heads, offsets, nxt, keys, K, flags)
     assert np.array_equal(nh, enh)
@@ -341,3 +341,15 @@ def test_short_list_malformations_leave_outputs(cutoff_setter):
         st, nh, got = gpu_sort_lists(heads, offs, bad, keys, 8)
         assert st == -2
         assert np.array_equal(got, np.full_like(bad, NIL))
+
+
+def test_shared_flag_batched(oracle_mod):
+    """PBIT_SHARED (tiles claimed in block start order) changes no result."""
+    rng = inputs.rng_for(4951)
+    lengths = inputs.log_uniform_lengths(400, 4, 16, rng, 16, 1 << 16)
+    nxt, heads, offs = inputs.slab_lists(lengths, rng)
+    keys = inputs.uniform_keys(nxt.shape[0], 32, rng)
+    keys[::3] = keys[0]
+    check(oracle_mod, heads, offs, nxt, keys, 8, shared=True)
+    check(oracle_mod, heads, offs, nxt, inputs.uniform_keys(nxt.shape[0], 64, rng), 4,
+          shared=True)

@@ -320,3 +320,19 @@ def test_2e26_u64_keys_with_payload(oracle_mod, K):
     assert np.array_equal(out, exp)
     assert np.array_equal(payload[out], payload[exp])
     del nxt, keys, payload, got
+
+
+@pytest.mark.parametrize("M,K,tile", [(32, 8, 6144), (64, 4, 8192), (16, 2, 6144)])
+def test_shared_flag_tiles_in_start_order(oracle_mod, M, K, tile):
+    """PBIT_SHARED hands tiles out in block start order; results are the
+    same, across tile boundaries and with ties."""
+    for n in (tile + 1, 3 * tile + 5, 40 * tile - 1):
+        say("shared M=%d K=%d n=%d" % (M, K, n))
+        rng = inputs.rng_for(9300 + n + M)
+        nxt, head, _ = inputs.random_list(n, rng)
+        keys = inputs.uniform_keys(n, M, rng)
+        keys[::5] = keys[1]
+        h, st, got = gpu_sort(head, nxt, keys, K, shared=True)
+        eh, enext = oracle_mod.sort_list(head, nxt, keys, M, K)
+        assert st == 0 and h == eh
+        assert np.array_equal(got, enext)
