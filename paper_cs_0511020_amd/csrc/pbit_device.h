@@ -113,7 +113,10 @@ template <typename KeyT, int RB> struct PassShape {
 // the device they can hold the XCDs such a tile needs; calls that expect that
 // take tiles from a ticket counter in block start order instead (PBIT_SHARED),
 // which never waits on a tile that has not started.
-constexpr uint32_t kPassChunk = 16;
+#ifndef PBIT_PASS_CHUNK
+#define PBIT_PASS_CHUNK 16
+#endif
+constexpr uint32_t kPassChunk = PBIT_PASS_CHUNK;
 
 __device__ __forceinline__ void set_error(int32_t* status, int32_t code)
 {
@@ -854,7 +857,10 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
         }
         // wrapping u32 arithmetic: position = j + (base - local start), the
         // base of SEG lists added per element
-        s_delta[d] = (SEG ? 0u : dbase[d]) + excl - s_start[d];
+        // (SEG: a tile inside one segment folds that segment's base in here;
+        // otherwise each element adds its own segment's base below)
+        const uint32_t base = SEG ? (nb == 0 ? sm.lbase[(size_t)seg0 * RADIX + d] : 0u) : dbase[d];
+        s_delta[d] = base + excl - s_start[d];
     }
     // stage the tile in LDS grouped by digit (stable)
 #pragma unroll
@@ -866,8 +872,10 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
             kv.key = key[i];
             kv.idx = idx[i];
             s_kv[pos] = kv;
-            if constexpr (SEG)
-                s_seg[pos] = (uint8_t)(dig[i] >> 9);
+            if constexpr (SEG) {
+                if (nb != 0)
+                    s_seg[pos] = (uint8_t)(dig[i] >> 9);
+            }
         }
     }
     __syncthreads();
@@ -879,8 +887,10 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
             const KV<KeyT> kv = s_kv[j];
             const uint32_t d = (uint32_t)(kv.key >> shift) & (RADIX - 1u);
             uint32_t g = j + s_delta[d];
-            if constexpr (SEG)
-                g += sm.lbase[(size_t)(seg0 + s_seg[j]) * RADIX + d];
+            if constexpr (SEG) {
+                if (nb != 0)
+                    g += sm.lbase[(size_t)(seg0 + s_seg[j]) * RADIX + d];
+            }
             if (g < n) {
                 if (out_pairs)
                     pout[g] = make_pair_kv<KeyT>(kv.key, kv.idx);

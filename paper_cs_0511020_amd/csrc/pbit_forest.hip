@@ -167,24 +167,24 @@ __global__ __launch_bounds__(1024) void k_fplan(ForestArgs F, uint32_t* __restri
     }
 }
 
-// Per list: the node -> list table over node indices and, for segments, the
-// position -> segment table over their position ranges (both at 256-entry
-// granularity: entry b names the list holding index b * 256).
+// One workgroup per list: the node -> list table over node indices and, for
+// segments, the position -> segment table over their position ranges (both
+// at 256-entry granularity: entry b names the list holding index b * 256).
 __global__ __launch_bounds__(256) void k_ftables(ForestArgs F, uint32_t* __restrict__ table,
                                                  uint32_t* __restrict__ ctable, Header* hdr)
 {
-    const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t l = blockIdx.x;
     if (l >= F.H || hdr->status != 0)
         return;
     const uint64_t lo = F.offsets[l], hi = F.offsets[l + 1];
     const uint64_t B = 1ull << F.lm.log_block;
-    for (uint64_t b = (lo + B - 1) / B; b < (hi + B - 1) / B; b++)
+    for (uint64_t b = (lo + B - 1) / B + threadIdx.x; b < (hi + B - 1) / B; b += blockDim.x)
         table[b] = l;
     if (is_seg(F, l)) {
         const uint32_t s = F.lrank[l];
         const uint64_t c0 = F.coff[s], c1 = c0 + (hi - lo);
         const uint64_t C = 1ull << kSegLog;
-        for (uint64_t b = (c0 + C - 1) / C; b < (c1 + C - 1) / C; b++)
+        for (uint64_t b = (c0 + C - 1) / C + threadIdx.x; b < (c1 + C - 1) / C; b += blockDim.x)
             ctable[b] = s;
     }
 }
@@ -1171,7 +1171,7 @@ hipError_t enqueue_sort_lists(const Plan& P, const uint32_t* heads, const uint64
                        (uint32_t*)(ws + P.o_headbits), hdr);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_ftables, dim3((P.num_lists + 255) / 256), dim3(256), 0, s, F,
+    hipLaunchKernelGGL(k_ftables, dim3(P.num_lists), dim3(256), 0, s, F,
                        (uint32_t*)(ws + P.o_table), (uint32_t*)(ws + P.o_ctable), hdr);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
