@@ -98,10 +98,16 @@ class GpuExecutor:
         stream = self.streams[self.next_stream]
         self.next_stream = (self.next_stream + 1) % len(self.streams)
         wsb = _lib.lists_workspace_bytes(total, L, M, self.K)
+        # pinned staging so that the small metadata copies are queued on the
+        # stream instead of stalling the host until the stream drains
+        h_meta = torch.empty((6, L + 1), dtype=torch.int64, pin_memory=True)
+        h_meta[:5, :L] = torch.from_numpy(meta)
+        h_meta[5] = torch.from_numpy(offs)
         with torch.cuda.stream(stream):
-            d_meta = torch.from_numpy(meta).to(self.device, non_blocking=False)
+            d_all = h_meta.to(self.device, non_blocking=True)
+            d_meta = d_all[:5, :L]
             d_heads = d_meta[0].to(torch.int32)
-            d_offs = torch.from_numpy(offs).to(self.device)
+            d_offs = d_all[5]
             ws = torch.empty(wsb, dtype=torch.uint8, device=self.device)
             new_heads = torch.empty(L, dtype=torch.int32, device=self.device)
             status = torch.zeros(1, dtype=torch.int32, device=self.device)
@@ -114,7 +120,7 @@ class GpuExecutor:
                 raise RuntimeError("batched launch failed: " + _lib.status_string(st))
             end = torch.cuda.Event(enable_timing=True)
             end.record(stream)
-        return {"batch": batch, "end": end, "keep": (d_meta, d_heads, d_offs, ws),
+        return {"batch": batch, "end": end, "keep": (h_meta, d_all, d_heads, ws),
                 "new_heads": new_heads, "status": status, "ws_bytes": wsb, "id": batch_id}
 
     def _launch_single(self, batch, batch_id):

@@ -319,6 +319,13 @@ def test_2e26_u64_keys_with_payload(oracle_mod, K):
     exp = definition_order(order, keys)
     assert np.array_equal(out, exp)
     assert np.array_equal(payload[out], payload[exp])
+    if K == 8:
+        # the oracle's recursion at this size, its groups below the top
+        # level on every host core (pinned against numpy like the sequential form)
+        say("oracle on host threads, n=2^26 u64")
+        eh, enext = oracle_mod.sort_list_threads(head, nxt, keys, 64, 8)
+        assert h == eh
+        assert np.array_equal(got, enext)
     del nxt, keys, payload, got
 
 
