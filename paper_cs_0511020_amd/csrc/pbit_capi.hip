@@ -189,10 +189,12 @@ bool make_plan(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, Plan* P)
     memset(P, 0, sizeof(*P));
     if (n > PBIT_MAX_NODES || !valid_shape(M, K))
         return false;
-    if (K == 0) {
-        uint32_t cut;
-        tune_lookup(0, M, n, &K, &cut);
-    }
+    // the table gives K (when 0 is passed) and the size up to which one
+    // workgroup sorts the whole list in LDS
+    uint32_t tuned_k, cut;
+    tune_lookup(0, M, n, &tuned_k, &cut);
+    if (K == 0)
+        K = tuned_k;
     if (n == 0) {
         size_t off;
         if (!plan_common(0, M, K, flags, 4, 0, 0, 0, P, off))
@@ -226,6 +228,7 @@ bool make_plan(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, Plan* P)
     }
     P->levels = k;
     P->total = off;
+    P->cutoff = valid_cutoff(cut) ? cut : 0u;
     return true;
 }
 

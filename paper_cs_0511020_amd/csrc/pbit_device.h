@@ -27,7 +27,10 @@ template <typename KeyT> __device__ __forceinline__ KeyT entry_key(const Entry<K
 // chain c's block of kPlane entries, so the first kPlane entries of all chains
 // (where most chains end: their mean length is 2^kLog0) are one dense array
 // that the walk fills and unchain reads nearly in order.
-constexpr uint32_t kPlane = 16;
+#ifndef PBIT_PLANE
+#define PBIT_PLANE 16
+#endif
+constexpr uint32_t kPlane = PBIT_PLANE;
 __device__ __forceinline__ size_t ent_at(uint32_t n_chains, uint32_t c, uint32_t t)
 {
     return (size_t)(t / kPlane) * ((size_t)n_chains * kPlane) + (size_t)c * kPlane + (t % kPlane);
@@ -900,5 +903,207 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
         }
     }
 }
+
+// ---------------------------------------------------------------- short lists
+// One workgroup sorts one list of at most CUT nodes entirely in LDS:
+//   1. its links (list-local) and keys are read once;
+//   2. pointer jumping (Wyllie) gives every node its distance to the end; the
+//      list is well formed iff, after ceil(log2 len) rounds, the head's
+//      pointer is NIL and its distance is len (its path then visits all len
+//      nodes); position = len - distance;
+//   3. the (key, node) pairs are placed in list order and split stably on
+//      every K-bit pattern, least significant first (ballot ranking per
+//      wave, counts scanned across waves), in LDS;
+//   4. the new links (list-local, NIL at the end) are built in LDS in index
+//      order.
+// Returns false for a malformed list (a link outside the list, or a head whose
+// path does not visit every node), true otherwise with `links` pointing at the
+// new links in LDS and `new_head` the list-local new head.  Called by every
+// thread of a kSmallThreads workgroup; `head` is list-local and below len.
+constexpr int kSmallThreads = 512;
+
+template <typename KeyT, int RB, int CUT>
+__device__ __forceinline__ bool small_sort(const uint32_t* __restrict__ nxt,
+                                           const KeyT* __restrict__ kp, uint32_t len,
+                                           uint32_t shift_in, uint32_t head, KeyT float_sel,
+                                           KeyT xor_mask, uint32_t passes,
+                                           const uint32_t*& links, uint32_t& new_head)
+{
+    constexpr int T = kSmallThreads;
+    constexpr int IT = CUT / T;
+    constexpr uint32_t WAVES = T / 64;
+    constexpr uint32_t RADIX = 1u << RB;
+    constexpr size_t RAW = sizeof(KV<KeyT>) > 8 ? sizeof(KV<KeyT>) : 8;
+    __shared__ __attribute__((aligned(16))) unsigned char s_raw[RAW * CUT];
+    __shared__ uint32_t s_next[CUT];
+    __shared__ uint32_t s_wave[WAVES][RADIX];
+    __shared__ uint32_t s_start[RADIX];
+    __shared__ int s_trivial;
+    uint2* s_ps = (uint2*)s_raw;        // ranking: (pointer, distance)
+    KV<KeyT>* s_kv = (KV<KeyT>*)s_raw;  // sorting: (key, node) in list order
+    const uint32_t tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+
+    uint32_t ptr[IT], dist[IT];
+    KeyT key[IT];
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < IT; k++) {
+        const uint32_t i = tid + k * T;
+        ptr[k] = kNil;
+        dist[k] = 0;
+        key[k] = 0;
+        if (i < len) {
+            uint32_t x = nxt[i];
+            if (x != kNil) {
+                x -= shift_in;  // wraps to >= len when outside the slab
+                if (x >= len) {
+                    bad = true;
+                    x = kNil;
+                }
+            }
+            ptr[k] = x;
+            dist[k] = 1;
+            key[k] = transform_key<KeyT>(kp[i], float_sel, xor_mask);
+            s_ps[i] = make_uint2(x, 1u);
+        }
+    }
+    __syncthreads();
+    uint32_t rounds = 0;
+    while ((1u << rounds) < len)
+        rounds++;
+    for (uint32_t r = 0; r < rounds; r++) {
+#pragma unroll
+        for (int k = 0; k < IT; k++) {
+            if (ptr[k] != kNil) {
+                const uint2 q = s_ps[ptr[k]];
+                ptr[k] = q.x;
+                dist[k] += q.y;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < IT; k++) {
+            const uint32_t i = tid + k * T;
+            if (i < len)
+                s_ps[i] = make_uint2(ptr[k], dist[k]);
+        }
+        __syncthreads();
+    }
+    const uint2 hq = s_ps[head];
+    bad |= hq.x != kNil || hq.y != len;
+    if (__syncthreads_or(bad))
+        return false;
+    // list order: the pair of node i goes to position len - dist
+#pragma unroll
+    for (int k = 0; k < IT; k++) {
+        const uint32_t i = tid + k * T;
+        if (i < len) {
+            KV<KeyT> kv;
+            kv.key = key[k];
+            kv.idx = i;
+            s_kv[len - dist[k]] = kv;
+        }
+    }
+    for (uint32_t i = tid; i < WAVES * RADIX; i += T)
+        (&s_wave[0][0])[i] = 0;
+    __syncthreads();
+    const uint64_t lt = lanemask_lt();
+    for (uint32_t p = 0; p < passes; p++) {
+        const uint32_t shift = p * RB;
+        KV<KeyT> kv[IT];
+        uint32_t dig[IT], rank[IT];
+#pragma unroll
+        for (int k = 0; k < IT; k++) {
+            const uint32_t e = wave * (64 * IT) + k * 64 + lane;
+            if (e < len) {
+                kv[k] = s_kv[e];
+                dig[k] = (uint32_t)(kv[k].key >> shift) & (RADIX - 1u);
+            } else {
+                kv[k].key = 0;
+                kv[k].idx = 0;
+                dig[k] = RADIX;
+            }
+        }
+        // ballot ranking in wave order, items in program order
+#pragma unroll
+        for (int k = 0; k < IT; k++) {
+            const bool valid = dig[k] < RADIX;
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < RB; b++) {
+                const bool bit = (dig[k] >> b) & 1u;
+                const uint64_t bb = __ballot(bit);
+                peers &= bit ? bb : ~bb;
+            }
+            const uint32_t below = (uint32_t)__popcll(peers & lt);
+            const uint32_t first = valid ? (uint32_t)(__ffsll((unsigned long long)peers) - 1) : lane;
+            uint32_t base = 0;
+            if (valid && below == 0)
+                base = atomicAdd(&s_wave[wave][dig[k]], (uint32_t)__popcll(peers));
+            rank[k] = __shfl(base, (int)first, 64) + below;
+        }
+        if (tid == 0)
+            s_trivial = 0;
+        __syncthreads();
+        for (uint32_t d = tid; d < RADIX; d += T) {
+            uint32_t sum = 0;
+#pragma unroll
+            for (uint32_t w = 0; w < WAVES; w++) {
+                const uint32_t v = s_wave[w][d];
+                s_wave[w][d] = sum;
+                sum += v;
+            }
+            s_start[d] = sum;
+            if (sum == len)
+                s_trivial = 1;  // every node has digit d: the pass is the identity
+        }
+        __syncthreads();
+        if (wave == 0) {
+            constexpr uint32_t PER = (RADIX + 63) / 64;
+            uint32_t vals[PER];
+            uint32_t local = 0;
+#pragma unroll
+            for (uint32_t j = 0; j < PER; j++) {
+                const uint32_t d = lane * PER + j;
+                vals[j] = d < RADIX ? s_start[d] : 0;
+                local += vals[j];
+            }
+            uint32_t incl = local;
+#pragma unroll
+            for (uint32_t off = 1; off < 64; off <<= 1) {
+                const uint32_t up = __shfl_up(incl, off, 64);
+                if (lane >= off)
+                    incl += up;
+            }
+            uint32_t run = incl - local;
+#pragma unroll
+            for (uint32_t j = 0; j < PER; j++) {
+                const uint32_t d = lane * PER + j;
+                if (d < RADIX)
+                    s_start[d] = run;
+                run += vals[j];
+            }
+        }
+        __syncthreads();
+        if (!s_trivial) {
+#pragma unroll
+            for (int k = 0; k < IT; k++)
+                if (dig[k] < RADIX)
+                    s_kv[s_start[dig[k]] + s_wave[wave][dig[k]] + rank[k]] = kv[k];
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < WAVES * RADIX; i += T)
+            (&s_wave[0][0])[i] = 0;
+        __syncthreads();
+    }
+    // new links in LDS, then out in index order
+    for (uint32_t j = tid; j < len; j += T)
+        s_next[s_kv[j].idx] = (j + 1 < len) ? s_kv[j + 1].idx : kNil;
+    new_head = s_kv[0].idx;
+    __syncthreads();
+    links = s_next;
+    return true;
+}
+
 
 }  // namespace pbit

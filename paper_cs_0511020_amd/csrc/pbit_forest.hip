@@ -343,20 +343,10 @@ __global__ __launch_bounds__(256) void k_fpack(Src src, ForestArgs F, uint32_t c
 }
 
 // ---------------------------------------------------------------- short lists
-// One workgroup sorts one list of at most CUT nodes entirely in LDS:
-//   1. its links (list-local) and keys are read once;
-//   2. pointer jumping (Wyllie) gives every node its distance to the end; the
-//      list is well formed iff, after ceil(log2 len) rounds, the head's
-//      pointer is NIL and its distance is len (its path then visits all len
-//      nodes); position = len - distance;
-//   3. the (key, node) pairs are placed in list order and split stably on
-//      every K-bit pattern, least significant first (ballot ranking per
-//      wave, counts scanned across waves), in LDS;
-//   4. the new links (list-local) are built in LDS and written to snext in
-//      index order, the new head to shead; the relink copies them to the
-//      caller's arrays once the whole batch is known to be valid.
-constexpr int kSmallThreads = 512;
-
+// A list of at most CUT nodes is sorted by one workgroup in LDS (small_sort);
+// its new links (list-local) go to snext in index order and its new head to
+// shead; k_fcommit copies them to the caller's arrays once the whole batch is
+// known to be valid.
 template <typename KeyT, int RB, int CUT>
 __global__ __launch_bounds__(kSmallThreads) void k_fsmall(ForestArgs F, const uint32_t* next_in,
                                                           const KeyT* keys, KeyT float_sel,
@@ -365,19 +355,6 @@ __global__ __launch_bounds__(kSmallThreads) void k_fsmall(ForestArgs F, const ui
                                                           uint32_t* __restrict__ shead,
                                                           Header* hdr)
 {
-    constexpr int T = kSmallThreads;
-    constexpr int IT = CUT / T;
-    constexpr uint32_t WAVES = T / 64;
-    constexpr uint32_t RADIX = 1u << RB;
-    constexpr size_t RAW = sizeof(KV<KeyT>) > 8 ? sizeof(KV<KeyT>) : 8;
-    __shared__ __attribute__((aligned(16))) unsigned char s_raw[RAW * CUT];
-    __shared__ uint32_t s_next[CUT];
-    __shared__ uint32_t s_wave[WAVES][RADIX];
-    __shared__ uint32_t s_start[RADIX];
-    __shared__ int s_trivial;
-    uint2* s_ps = (uint2*)s_raw;        // ranking: (pointer, distance)
-    KV<KeyT>* s_kv = (KV<KeyT>*)s_raw;  // sorting: (key, node) in list order
-
     const uint32_t l = blockIdx.x;
     if (l >= F.H)
         return;
@@ -387,176 +364,23 @@ __global__ __launch_bounds__(kSmallThreads) void k_fsmall(ForestArgs F, const ui
     if (hi <= lo || hi - lo > CUT || hi - lo > F.cutoff)
         return;
     const uint32_t len = (uint32_t)(hi - lo);
-    const uint32_t tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
     const uint32_t* nxt = F.next_in_ptrs ? (const uint32_t*)F.next_in_ptrs[l] : next_in + lo;
     const KeyT* kp = F.next_in_ptrs ? (const KeyT*)F.key_ptrs[l] : keys + lo;
     const uint32_t shift_in = F.next_in_ptrs ? 0u : (uint32_t)lo;  // global -> local
-
-    uint32_t ptr[IT], dist[IT];
-    KeyT key[IT];
-    bool bad = false;
-#pragma unroll
-    for (int k = 0; k < IT; k++) {
-        const uint32_t i = tid + k * T;
-        ptr[k] = kNil;
-        dist[k] = 0;
-        key[k] = 0;
-        if (i < len) {
-            uint32_t x = nxt[i];
-            if (x != kNil) {
-                x -= shift_in;  // wraps to >= len when outside the slab
-                if (x >= len) {
-                    bad = true;
-                    x = kNil;
-                }
-            }
-            ptr[k] = x;
-            dist[k] = 1;
-            key[k] = transform_key<KeyT>(kp[i], float_sel, xor_mask);
-            s_ps[i] = make_uint2(x, 1u);
-        }
-    }
-    __syncthreads();
-    uint32_t rounds = 0;
-    while ((1u << rounds) < len)
-        rounds++;
-    for (uint32_t r = 0; r < rounds; r++) {
-#pragma unroll
-        for (int k = 0; k < IT; k++) {
-            if (ptr[k] != kNil) {
-                const uint2 q = s_ps[ptr[k]];
-                ptr[k] = q.x;
-                dist[k] += q.y;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < IT; k++) {
-            const uint32_t i = tid + k * T;
-            if (i < len)
-                s_ps[i] = make_uint2(ptr[k], dist[k]);
-        }
-        __syncthreads();
-    }
+    // the head was checked against the slab before (k_fplan)
     const uint32_t h = head_of(F, l, lo) - (uint32_t)lo;
-    const uint2 hq = s_ps[h];
-    bad |= hq.x != kNil || hq.y != len;
-    if (__syncthreads_or(bad)) {
-        if (tid == 0)
+    const uint32_t* links;
+    uint32_t new_head;
+    if (!small_sort<KeyT, RB, CUT>(nxt, kp, len, shift_in, h, float_sel, xor_mask, passes, links,
+                                   new_head)) {
+        if (threadIdx.x == 0)
             set_error(&hdr->status, PBIT_EMALFORMED);
         return;
     }
-    // list order: the pair of node i goes to position len - dist
-#pragma unroll
-    for (int k = 0; k < IT; k++) {
-        const uint32_t i = tid + k * T;
-        if (i < len) {
-            KV<KeyT> kv;
-            kv.key = key[k];
-            kv.idx = i;
-            s_kv[len - dist[k]] = kv;
-        }
-    }
-    for (uint32_t i = tid; i < WAVES * RADIX; i += T)
-        (&s_wave[0][0])[i] = 0;
-    __syncthreads();
-    const uint64_t lt = lanemask_lt();
-    for (uint32_t p = 0; p < passes; p++) {
-        const uint32_t shift = p * RB;
-        KV<KeyT> kv[IT];
-        uint32_t dig[IT], rank[IT];
-#pragma unroll
-        for (int k = 0; k < IT; k++) {
-            const uint32_t e = wave * (64 * IT) + k * 64 + lane;
-            if (e < len) {
-                kv[k] = s_kv[e];
-                dig[k] = (uint32_t)(kv[k].key >> shift) & (RADIX - 1u);
-            } else {
-                kv[k].key = 0;
-                kv[k].idx = 0;
-                dig[k] = RADIX;
-            }
-        }
-        // ballot ranking in wave order, items in program order
-#pragma unroll
-        for (int k = 0; k < IT; k++) {
-            const bool valid = dig[k] < RADIX;
-            uint64_t peers = __ballot(valid);
-#pragma unroll
-            for (int b = 0; b < RB; b++) {
-                const bool bit = (dig[k] >> b) & 1u;
-                const uint64_t bb = __ballot(bit);
-                peers &= bit ? bb : ~bb;
-            }
-            const uint32_t below = (uint32_t)__popcll(peers & lt);
-            const uint32_t first = valid ? (uint32_t)(__ffsll((unsigned long long)peers) - 1) : lane;
-            uint32_t base = 0;
-            if (valid && below == 0)
-                base = atomicAdd(&s_wave[wave][dig[k]], (uint32_t)__popcll(peers));
-            rank[k] = __shfl(base, (int)first, 64) + below;
-        }
-        if (tid == 0)
-            s_trivial = 0;
-        __syncthreads();
-        for (uint32_t d = tid; d < RADIX; d += T) {
-            uint32_t sum = 0;
-#pragma unroll
-            for (uint32_t w = 0; w < WAVES; w++) {
-                const uint32_t v = s_wave[w][d];
-                s_wave[w][d] = sum;
-                sum += v;
-            }
-            s_start[d] = sum;
-            if (sum == len)
-                s_trivial = 1;  // every node has digit d: the pass is the identity
-        }
-        __syncthreads();
-        if (wave == 0) {
-            constexpr uint32_t PER = (RADIX + 63) / 64;
-            uint32_t vals[PER];
-            uint32_t local = 0;
-#pragma unroll
-            for (uint32_t j = 0; j < PER; j++) {
-                const uint32_t d = lane * PER + j;
-                vals[j] = d < RADIX ? s_start[d] : 0;
-                local += vals[j];
-            }
-            uint32_t incl = local;
-#pragma unroll
-            for (uint32_t off = 1; off < 64; off <<= 1) {
-                const uint32_t up = __shfl_up(incl, off, 64);
-                if (lane >= off)
-                    incl += up;
-            }
-            uint32_t run = incl - local;
-#pragma unroll
-            for (uint32_t j = 0; j < PER; j++) {
-                const uint32_t d = lane * PER + j;
-                if (d < RADIX)
-                    s_start[d] = run;
-                run += vals[j];
-            }
-        }
-        __syncthreads();
-        if (!s_trivial) {
-#pragma unroll
-            for (int k = 0; k < IT; k++)
-                if (dig[k] < RADIX)
-                    s_kv[s_start[dig[k]] + s_wave[wave][dig[k]] + rank[k]] = kv[k];
-        }
-        __syncthreads();
-        for (uint32_t i = tid; i < WAVES * RADIX; i += T)
-            (&s_wave[0][0])[i] = 0;
-        __syncthreads();
-    }
-    // new links in LDS, then out in index order
-    for (uint32_t j = tid; j < len; j += T)
-        s_next[s_kv[j].idx] = (j + 1 < len) ? s_kv[j + 1].idx : kNil;
-    __syncthreads();
-    for (uint32_t i = tid; i < len; i += T)
-        snext[lo + i] = s_next[i];
-    if (tid == 0)
-        shead[l] = s_kv[0].idx;
+    for (uint32_t i = threadIdx.x; i < len; i += kSmallThreads)
+        snext[lo + i] = links[i];
+    if (threadIdx.x == 0)
+        shead[l] = new_head;
 }
 
 // ---------------------------------------------------------------- ranking

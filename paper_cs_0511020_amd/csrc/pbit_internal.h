@@ -100,7 +100,7 @@ enum Stage : int32_t {
     kStageZero = 0, kStagePack, kStageWalk0, kStageWalkUp, kStageBase, kStageDown,
     kStageUnchain, kStageSchedule, kStagePass, kStageRelink,
     kStagePlan,   // many-list sorts: slab checks, segments, tables
-    kStageSmall,  // many-list sorts: short lists sorted in LDS
+    kStageSmall,  // short lists sorted in LDS (one list, or the short ones of many)
     kStageBases,  // many-list sorts: per-list digit bases
     kStageCommit, // many-list sorts: short lists' results copied out
     kStageCount

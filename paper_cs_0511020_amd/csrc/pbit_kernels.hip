@@ -369,11 +369,87 @@ static hipError_t enqueue_after_pack(const Plan& P, uint32_t head, char* out_bas
                                      uint64_t out_stride, uint32_t* d_result, char* ws,
                                      hipStream_t s, Prof* prof);
 
+// ---------------------------------------------------------------- short list
+// A list of at most CUT nodes (and at most the tuned cutoff): the whole sort
+// by one workgroup in LDS (small_sort), one launch instead of the device-wide
+// path.  Every link is read before any is written, so next_out may be
+// next_in.  A malformed list leaves next_out untouched; the result is
+// {new head, PBIT_OK} or {NIL, PBIT_EMALFORMED}, as from the relink.
+template <typename KeyT, int RB, int CUT>
+__global__ __launch_bounds__(kSmallThreads) void k_small_list(uint32_t head,
+                                                              const uint32_t* next_in,
+                                                              uint32_t* next_out, const KeyT* keys,
+                                                              uint32_t n, KeyT float_sel,
+                                                              KeyT xor_mask, uint32_t passes,
+                                                              uint32_t* __restrict__ result)
+{
+    const uint32_t* links;
+    uint32_t new_head;
+    if (!small_sort<KeyT, RB, CUT>(next_in, keys, n, 0u, head, float_sel, xor_mask, passes, links,
+                                   new_head)) {
+        if (threadIdx.x == 0) {
+            result[0] = kNil;
+            result[1] = (uint32_t)PBIT_EMALFORMED;
+        }
+        return;
+    }
+    for (uint32_t i = threadIdx.x; i < n; i += kSmallThreads)
+        next_out[i] = links[i];
+    if (threadIdx.x == 0) {
+        result[0] = new_head;
+        result[1] = 0;
+    }
+}
+
+constexpr uint32_t kSmallListMax = 4096;
+
+template <typename KeyT, int RB>
+static hipError_t launch_small_rb(const Plan& P, uint32_t head, const uint32_t* next_in,
+                                  uint32_t* next_out, const void* keys, uint32_t* d_result,
+                                  hipStream_t s)
+{
+    const KeyT float_sel = key_float_sel<KeyT>(P.flags), mask = key_xor_mask<KeyT>(P.flags);
+    if (P.n <= 1024)
+        hipLaunchKernelGGL((k_small_list<KeyT, RB, 1024>), dim3(1), dim3(kSmallThreads), 0, s,
+                           head, next_in, next_out, (const KeyT*)keys, (uint32_t)P.n, float_sel,
+                           mask, P.passes, d_result);
+    else
+        hipLaunchKernelGGL((k_small_list<KeyT, RB, kSmallListMax>), dim3(1), dim3(kSmallThreads),
+                           0, s, head, next_in, next_out, (const KeyT*)keys, (uint32_t)P.n,
+                           float_sel, mask, P.passes, d_result);
+    return hipGetLastError();
+}
+
+template <typename KeyT>
+static hipError_t launch_small(const Plan& P, uint32_t head, const uint32_t* next_in,
+                               uint32_t* next_out, const void* keys, uint32_t* d_result,
+                               hipStream_t s)
+{
+    switch (P.RB) {
+    case 1: return launch_small_rb<KeyT, 1>(P, head, next_in, next_out, keys, d_result, s);
+    case 2: return launch_small_rb<KeyT, 2>(P, head, next_in, next_out, keys, d_result, s);
+    case 4: return launch_small_rb<KeyT, 4>(P, head, next_in, next_out, keys, d_result, s);
+    default: return launch_small_rb<KeyT, 8>(P, head, next_in, next_out, keys, d_result, s);
+    }
+}
+
 // The whole path queued on one stream.
 hipError_t enqueue_sort(const Plan& P, uint32_t head, const uint32_t* next_in, uint32_t* next_out,
                         const void* keys, uint32_t* d_result, char* ws, hipStream_t s, Prof* prof)
 {
     hipError_t e;
+    if (P.n <= P.cutoff && P.n <= kSmallListMax) {
+        mark(prof, s, kStageSmall);
+        switch (P.key_bytes) {
+        case 1: e = launch_small<uint8_t>(P, head, next_in, next_out, keys, d_result, s); break;
+        case 2: e = launch_small<uint16_t>(P, head, next_in, next_out, keys, d_result, s); break;
+        case 4: e = launch_small<uint32_t>(P, head, next_in, next_out, keys, d_result, s); break;
+        default: e = launch_small<uint64_t>(P, head, next_in, next_out, keys, d_result, s); break;
+        }
+        if (e == hipSuccess)
+            mark(prof, s, kStageCount);
+        return e;
+    }
     mark(prof, s, kStageZero);
     if ((e = launch_zero(P, ws, s)) != hipSuccess)
         return e;

@@ -4,19 +4,22 @@ The paper weighs the pattern length (Sec. 10): a longer pattern means fewer
 passes over the list but more groups per pass.  On the GPU a pass moves every
 (key, node) pair once, so fewer passes usually win, but a wider pattern also
 means larger per-tile tables and, for many lists, larger per-list digit
-tables; and in a batch the cutoff decides which lists are sorted by one
-workgroup in on-chip memory and which take the device-wide passes.  This
-module times the library on the device for each candidate and writes the
-fastest choices:
+tables.  The cutoff (Sec. 9 weighs methods by list length) decides which
+lists are sorted by one workgroup in on-chip memory and which take the
+device-wide path: the short lists of a batch, and a single list of at most
+that many nodes.  This module times the library on the device for each
+candidate and writes the fastest choices:
 
 * ``pbit_tuning.h`` -- the library's built-in table (entries
   {kind, M, n_max, K, cutoff}; kind 0 one list, 1 many lists), compiled into
   libpbit by the next build;
 * ``tuning.json`` -- the same choices with every timing behind them.
 
-Workloads: single lists of 2^12, 2^16, 2^20 and 2^24 nodes, uniform keys,
-random layout; batches of lists with lengths log-uniform in [16, 2^16]
-(the batched benchmark's distribution) at about 2^20, 2^24 and 2^27 nodes.
+Workloads: single lists of 2^10, 2^11, 2^12, 2^16, 2^20 and 2^24 nodes,
+uniform keys, random layout (the cutoff is timed on the lists of at most
+4096 nodes, the largest one workgroup takes); batches of lists with lengths
+log-uniform in [16, 2^16] (the batched benchmark's distribution) at about
+2^20, 2^24 and 2^27 nodes.
 Every input is generated on the device from fixed seeds.  Times are medians
 of HIP-event intervals around the sort on its stream.
 
@@ -34,7 +37,8 @@ import time
 from . import _lib
 
 NMAX = 0xFFFFFFFF
-SINGLE_SIZES = (1 << 12, 1 << 16, 1 << 20, 1 << 24)
+SINGLE_SIZES = (1 << 10, 1 << 11, 1 << 12, 1 << 16, 1 << 20, 1 << 24)
+SHORT_MAX = 4096  # the longest single list one workgroup sorts
 BATCH_NODES = (1 << 20, 1 << 24, 1 << 27)
 CUTOFFS = (1024, 2048, 4096)
 WIDTHS = (8, 16, 32, 64)
@@ -72,7 +76,9 @@ def _median_ms(torch, fn, reps: int, warm: int = 2) -> float:
 
 
 def time_single(torch, M: int, n: int, reps: int):
-    """{K: ms} for one list of n nodes with uniform M-bit keys."""
+    """{(K, cutoff): ms} for one list of n nodes with uniform M-bit keys.  The
+    cutoff only matters up to SHORT_MAX nodes; above, the largest one is
+    recorded (it keeps neighbouring table entries mergeable)."""
     dev = torch.device("cuda")
     g = torch.Generator(device=dev)
     g.manual_seed(7000 + M + n)
@@ -85,20 +91,68 @@ def time_single(torch, M: int, n: int, reps: int):
     out = torch.empty_like(nxt)
     res = torch.zeros(2, dtype=torch.int32, device=dev)
     times = {}
-    for K in k_candidates(M):
-        wsb = _lib.workspace_bytes(n, M, K)
-        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    cuts = CUTOFFS if n <= SHORT_MAX else (CUTOFFS[-1],)
+    try:
+        for K in k_candidates(M):
+            wsb = _lib.workspace_bytes(n, M, K)
+            ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+            for cut in cuts:
+                # an entry for exactly this size wins over any wider one
+                if _lib.tune_set(0, M, n, K, cut) != _lib.OK:
+                    raise RuntimeError("tuning entry rejected")
 
-        def run():
-            st = _lib.sort_list_async(head, nxt, out, keys, n, M, K, 0, res, ws, wsb)
-            if st != _lib.OK:
-                raise RuntimeError(_lib.status_string(st))
+                def run():
+                    st = _lib.sort_list_async(head, nxt, out, keys, n, M, K, 0, res, ws, wsb)
+                    if st != _lib.OK:
+                        raise RuntimeError(_lib.status_string(st))
 
-        times[K] = _median_ms(torch, run, reps)
-        if int(res[1].item()) != 0:
-            raise RuntimeError("device status %d" % int(res[1].item()))
-        del ws
+                times[(K, cut)] = _median_ms(torch, run, reps)
+                if int(res[1].item()) != 0:
+                    raise RuntimeError("device status %d" % int(res[1].item()))
+            del ws
+    finally:
+        _lib.tune_reset()
     return times
+
+
+TIE = 0.02  # timings this close are treated as equal
+
+
+def pick_single(times):
+    """The (K, cutoff) of a single-list timing: the fastest, except that
+    choices within TIE of it count as equal and the largest cutoff among them
+    wins.  At a size below two cutoffs both send the list down the same path,
+    so only noise tells them apart; the larger one keeps the next sizes on
+    the one-workgroup path too."""
+    best = min(times.values())
+    near = [kc for kc, v in times.items() if v <= best * (1 + TIE)]
+    return max(near, key=lambda kc: (kc[1], -times[kc]))
+
+
+def _parse_ms(ms):
+    import re
+    out = {}
+    for key, v in ms.items():
+        m = re.fullmatch(r"K(\d+)_cut(\d+)", key)
+        out[(int(m.group(1)), int(m.group(2)))] = float(v)
+    return out
+
+
+def entries_from_record(record):
+    """Table entries from a saved timing record (tuning.json)."""
+    entries = []
+    for kind, rows, size_key, pick in ((0, record["single"], "n", pick_single),
+                                       (1, record["batched"], "nodes",
+                                        lambda t: min(t, key=t.get))):
+        for M in WIDTHS:
+            best = []
+            for r in rows:
+                if r["M"] == M:
+                    r["K"], r["cutoff"] = pick(_parse_ms(r["ms"]))
+                    best.append((r[size_key], r["K"], r["cutoff"]))
+            if best:
+                entries += entries_from_best(kind, M, best)
+    return entries
 
 
 def batch_lengths(total: int, seed: int):
@@ -197,7 +251,7 @@ def run(out_dir: str, quick: bool = False):
     _lib.load()
     _lib.tune_reset()
     reps = 5 if quick else 10
-    single_sizes = SINGLE_SIZES[:3] if quick else SINGLE_SIZES
+    single_sizes = SINGLE_SIZES[:5] if quick else SINGLE_SIZES
     batch_nodes = BATCH_NODES[:2] if quick else BATCH_NODES
     record = {"single": [], "batched": [], "device": torch.cuda.get_device_name(0),
               "when": time.strftime("%Y-%m-%d %H:%M:%S")}
@@ -206,12 +260,12 @@ def run(out_dir: str, quick: bool = False):
         best = []
         for n in single_sizes:
             t = time_single(torch, M, n, reps)
-            K = min(t, key=t.get)
-            best.append((n, K, 2048))
-            record["single"].append({"M": M, "n": n, "ms": {str(k): round(v, 4)
-                                                            for k, v in t.items()},
-                                     "K": K})
-            print("single M=%d n=%d %s -> K=%d" % (M, n, t, K), flush=True)
+            K, cut = pick_single(t)
+            best.append((n, K, cut))
+            record["single"].append({"M": M, "n": n,
+                                     "ms": {"K%d_cut%d" % kc: round(v, 4) for kc, v in t.items()},
+                                     "K": K, "cutoff": cut})
+            print("single M=%d n=%d %s -> K=%d cutoff=%d" % (M, n, t, K, cut), flush=True)
         entries += entries_from_best(0, M, best)
     for M in WIDTHS:
         best = []
@@ -235,12 +289,30 @@ def run(out_dir: str, quick: bool = False):
     return record
 
 
+def write_from_record(json_path: str, out_dir: str):
+    """Rewrite pbit_tuning.h from a saved record, without a GPU."""
+    with open(json_path) as f:
+        record = json.load(f)
+    entries = entries_from_record(record)
+    record["entries"] = entries
+    os.makedirs(out_dir, exist_ok=True)
+    with open(os.path.join(out_dir, "pbit_tuning.h"), "w") as f:
+        f.write(render_header(entries))
+    with open(os.path.join(out_dir, "tuning.json"), "w") as f:
+        json.dump(record, f, indent=1)
+    return entries
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--out-dir", default="tuning_out")
     ap.add_argument("--quick", action="store_true", help="fewer sizes and repetitions")
+    ap.add_argument("--from-json", help="rebuild the table from a saved tuning.json instead")
     args = ap.parse_args()
-    run(args.out_dir, args.quick)
+    if args.from_json:
+        write_from_record(args.from_json, args.out_dir)
+    else:
+        run(args.out_dir, args.quick)
 
 
 if __name__ == "__main__":

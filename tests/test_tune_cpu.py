@@ -37,3 +37,24 @@ def test_committed_table_is_valid_and_applied():
         assert x["cutoff"] in (1024, 2048, 4096)
         # the library answers with the entry that covers its own n_max
         assert _lib.tune_lookup(x["kind"], x["M"], x["n_max"]) == (x["K"], x["cutoff"])
+
+
+def test_single_list_ties_prefer_the_larger_cutoff():
+    # at 2048 nodes cutoffs 2048 and 4096 both take the one-workgroup path:
+    # only noise separates them, and the larger one must win
+    t = {(8, 1024): 0.064, (8, 2048): 0.0270, (8, 4096): 0.0272, (4, 4096): 0.0326}
+    assert tune.pick_single(t) == (8, 4096)
+    # a real difference is kept
+    t = {(8, 1024): 0.020, (8, 4096): 0.030}
+    assert tune.pick_single(t) == (8, 1024)
+
+
+def test_table_rebuilt_from_saved_timings(tmp_path):
+    """The committed table is what the committed timings give."""
+    with open(os.path.join(ROOT, "paper_cs_0511020_amd", "csrc", "pbit_tuning.h")) as f:
+        committed = tune.parse_header(f.read())
+    entries = tune.write_from_record(os.path.join(ROOT, "paper_cs_0511020_amd", "tuning.json"),
+                                     str(tmp_path))
+    assert entries == committed
+    # every single-list entry sends lists of up to 4096 nodes to one workgroup
+    assert all(e["cutoff"] == 4096 for e in entries if e["kind"] == 0)
