@@ -216,6 +216,29 @@ def test_long_chains(oracle_mod):
         run_parity(oracle_mod, head, nxt, keys.astype(np.uint64) * 3, 4)
 
 
+def test_long_upper_level_chains(oracle_mod):
+    """Chains of the first upper ranking level start at the level-0 chains
+    whose index is a multiple of 4, i.e. at nodes j with j mod 64 = 48.  Moving
+    all but `keep` evenly spread ones of those nodes to the end of the list
+    makes upper chains of hundreds or thousands of elements, longer than the
+    elements their upward walk keeps, so the downward pass walks their rests
+    again."""
+    rng = inputs.rng_for(67)
+    for n, keep in [(200000, 3), (200000, 40), (1 << 20, 200)]:
+        say("long upper chains n=%d keep=%d" % (n, keep))
+        order = rng.permutation(n).astype(np.uint32)
+        starts = (order % 64) == 48
+        idx = np.flatnonzero(starts)
+        late = np.zeros(n, dtype=bool)
+        late[idx] = True
+        late[idx[np.linspace(0, len(idx) - 1, keep).astype(np.int64)]] = False
+        order = np.concatenate([order[~late], order[late]])
+        nxt, head = inputs.links_from_order(order)
+        keys = inputs.uniform_keys(n, 32, rng)
+        keys[::9] = keys[4]
+        run_parity(oracle_mod, head, nxt, keys, 8)
+
+
 def test_malformed_lists_are_rejected_untouched():
     rng = inputs.rng_for(71)
     n = 30000
