@@ -466,10 +466,51 @@ def run_extras(args, lib, torch, np, inputs, bytemodel):
                                    "correct": okp}
         del pws
     del pnext_in, pnext_out, pkeys_d
+    # short single lists: one workgroup sorts the whole list in LDS (lists of
+    # at most the tuned cutoff); each size also timed on the device-wide path
+    # (a cutoff below the size, through the tuning table) for comparison
+    short = {}
+    try:
+        for sn in (1024, 4096):
+            srng = inputs.rng_for(2501 + sn)
+            snxt, shead, sorder = inputs.random_list(sn, srng)
+            skeys = inputs.uniform_keys(sn, 32, srng)
+            sn_in = torch.from_numpy(snxt.view(np.int32)).to(dev)
+            sn_out = torch.empty_like(sn_in)
+            sk_d = torch.from_numpy(skeys.view(np.int32)).to(dev)
+            sws_bytes = _lib.workspace_bytes(sn, 32, 8)
+            sws = torch.empty(sws_bytes, dtype=torch.uint8, device=dev)
+            sexp = sorder[np.argsort(skeys[sorder], kind="stable")]
+            row = {}
+            for name, cut in (("one_workgroup", 4096), ("device_wide", 1024 if sn > 1024 else None)):
+                if cut is None:
+                    continue
+                _lib.tune_clear()
+                if _lib.tune_set(0, 32, 0xFFFFFFFF, 8, cut) != 0:
+                    raise RuntimeError("tuning entry rejected")
+
+                def sort_short():
+                    st = _lib.sort_list_async(shead, sn_in, sn_out, sk_d, sn, 32, 8, 0, result,
+                                              sws, sws_bytes, stream)
+                    if st != 0:
+                        raise RuntimeError("short sort failed: " + _lib.status_string(st))
+
+                sms = timed(sort_short)
+                hs = int(result[0].item()) & 0xFFFFFFFF
+                gots = sn_out.cpu().numpy().view(np.uint32)
+                oks = hs == int(sexp[0]) and bool(np.array_equal(gots[sexp[:-1]], sexp[1:]))
+                row[name] = {"us": round(sms * 1e3, 1), "correct": oks}
+            short["n%d" % sn] = row
+            del sws, sn_in, sn_out, sk_d
+    finally:
+        _lib.tune_reset()
     rep_bytes = 8 * n + 4
     rep_gbs = rep_bytes / (rep_ms * 1e-3) / 1e9
     del ws, next_in
     return {
+        "short_lists": dict(workload="single lists of 1024 and 4096 nodes, u32 uniform keys, "
+                                     "K=8: the one-workgroup sort in LDS (cutoff 4096) and, at "
+                                     "4096, the device-wide path (cutoff 1024)", **short),
         "float32_keys": {"workload": "single list n=%d binary32 keys, log-uniform magnitudes of "
                                      "both signs, 25%% repeats, K=%d" % (n, Kshow),
                          "ms": round(sort_ms, 4), "Mnodes_per_s": round(n / (sort_ms * 1e-3) / 1e6, 1),

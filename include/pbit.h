@@ -273,15 +273,19 @@ int pbit_repair_prev_async(const uint32_t *d_heads, uint32_t num_lists, const ui
 uint32_t pbit_set_lookback_spin_limit(uint32_t sleeps);
 
 /*
- * Tuning (Sec. 10 weighs the pattern length K against the work per pass).
- * When K = 0 is passed, the library picks K, and every many-list sort picks
- * its short-list cutoff, from a table of measured choices: an entry applies
- * to sorts of its kind (0: one list, 1: many lists) and key width M whose
- * node count (for many lists: the total) is at most n_max; the entry with the
- * smallest such n_max wins, else K = 8 (4 for M = 8) and cutoff 2048.  Lists
- * of at most `cutoff` nodes in a many-list sort are each sorted by one
- * workgroup in on-chip memory; cutoff is 1024, 2048 or 4096.  The table is
- * built in (from device measurements) and process-wide.
+ * Tuning (Sec. 10 weighs the pattern length K against the work per pass;
+ * Sec. 9 weighs methods by list length).  When K = 0 is passed, the library
+ * picks K, and every sort picks its short-list cutoff, from a table of
+ * measured choices: an entry applies to sorts of its kind (0: one list, 1:
+ * many lists) and key width M whose node count (for many lists: the total)
+ * is at most n_max; the entry with the smallest such n_max wins, else K = 8
+ * (4 for M = 8) and cutoff 2048.  Lists of at most `cutoff` nodes in a
+ * many-list sort, and a single list of at most `cutoff` nodes (whatever K
+ * the caller passes), are each sorted by one workgroup in on-chip memory in
+ * one launch; cutoff is 1024, 2048 or 4096.  The result does not depend on
+ * the path.  The table is built in (from device measurements) and
+ * process-wide.  Records (pbit_sort_list_aos_async) always take the
+ * device-wide path.
  *   pbit_tune_set     adds or replaces the entry (kind, M, n_max); returns
  *                     PBIT_OK, PBIT_EINVAL (kind > 1, K not in {1,2,4,8} or
  *                     not dividing M, bad cutoff) or PBIT_ENOMEM (table full)
