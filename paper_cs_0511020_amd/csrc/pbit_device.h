@@ -633,6 +633,12 @@ template <> struct Look<uint64_t> {
 
 template <typename SKey> struct KV { SKey key; uint32_t idx; };
 
+// Look-back words read per round trip by a digit's thread.
+#ifndef PBIT_LOOK_WINDOW
+#define PBIT_LOOK_WINDOW 4
+#endif
+constexpr uint32_t kLookWindow = PBIT_LOOK_WINDOW;
+
 template <typename KeyT, int RB, int BLOCK, int ITEMS, typename LW, bool SEG>
 __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_pass(
     uint32_t pass, uint32_t shift, uint32_t n_all, Pair<KeyT>* __restrict__ pairsA,
@@ -825,34 +831,54 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
     for (uint32_t i = tid; i < WAVES * RADIX; i += BLOCK)
         (&s_wave[0][0])[i] += s_start[i % RADIX];
     __syncthreads();
-    // decoupled look-back per digit
+    // decoupled look-back per digit, kLookWindow predecessors per round trip:
+    // the window's words are loaded together and consumed in tile order up to
+    // the first inclusive prefix; an unpublished word stops the consumption
+    // there (later words of the window are not used past it)
     for (uint32_t d = tid; d < RADIX; d += BLOCK) {
         uint32_t excl = 0;
         if (tile != 0) {
-            int64_t j = (int64_t)tile - 1;
+            int64_t j = (int64_t)tile - 1;  // the next predecessor to add
             uint32_t spins = 0;
-            while (j >= 0) {
-                const LW v = ld_agent(&look[(size_t)j * RADIX + d]);
-                const LW f = v & ~LK::MASK;
-                if (f == 0) {
-                    if (++spins <= spin_limit) {
-                        __builtin_amdgcn_s_sleep(1);
+            bool done = false;
+            while (!done && j >= 0) {
+                LW v[kLookWindow];
+#pragma unroll
+                for (uint32_t w = 0; w < kLookWindow; w++)
+                    v[w] = (j >= (int64_t)w) ? ld_agent(&look[(size_t)(j - w) * RADIX + d]) : (LW)0;
+                uint32_t used = 0;
+                bool blocked = false;
+#pragma unroll
+                for (uint32_t w = 0; w < kLookWindow; w++) {
+                    if (done || blocked || j < (int64_t)w)
+                        continue;
+                    const LW f = v[w] & ~LK::MASK;
+                    if (f == 0) {
+                        blocked = true;
                         continue;
                     }
-                    // predecessor not running yet: count its digit d directly
-                    const uint64_t b0 = (uint64_t)j * TILE;
-                    const uint64_t b1 = min<uint64_t>(b0 + TILE, (uint64_t)n);
-                    uint32_t c = 0;
-                    for (uint64_t q = b0; q < b1; q++)
-                        c += ((uint32_t)(pair_key<KeyT>(pin[q]) >> shift) & (RADIX - 1u)) == d;
-                    excl += c;
-                    j--;
+                    excl += (uint32_t)(v[w] & LK::MASK);
+                    used = w + 1;
+                    if (f == LK::PREFIX)
+                        done = true;
+                }
+                j -= used;
+                if (done || used > 0) {
                     spins = 0;
                     continue;
                 }
-                excl += (uint32_t)(v & LK::MASK);
-                if (f == LK::PREFIX)
-                    break;
+                // predecessor j has published nothing yet
+                if (++spins <= spin_limit) {
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                // predecessor not running yet: count its digit d directly
+                const uint64_t b0 = (uint64_t)j * TILE;
+                const uint64_t b1 = min<uint64_t>(b0 + TILE, (uint64_t)n);
+                uint32_t c = 0;
+                for (uint64_t q = b0; q < b1; q++)
+                    c += ((uint32_t)(pair_key<KeyT>(pin[q]) >> shift) & (RADIX - 1u)) == d;
+                excl += c;
                 j--;
                 spins = 0;
             }
