@@ -227,6 +227,14 @@ bool make_plan(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, Plan* P)
         k++;
     }
     P->levels = k;
+    // relink through node ranges held in LDS (see k_relink_ranges)
+    if (n >= kRelinkMinNodes && n <= kRelinkMaxNodes) {
+        P->relink_r = n <= (uint64_t)kRelinkRangesMax << 14 ? 14u : 15u;
+        P->relink_ranges = (uint32_t)ceil_div(n, 1ull << P->relink_r);
+        P->relink_tiles = (uint32_t)ceil_div(n, kRelinkTile);
+        P->o_rstart = off;
+        off = align_up(off + (size_t)(P->relink_ranges + 1) * P->relink_tiles * 4);
+    }
     P->total = off;
     P->cutoff = valid_cutoff(cut) ? cut : 0u;
     return true;

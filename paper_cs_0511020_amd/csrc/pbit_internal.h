@@ -26,6 +26,13 @@ constexpr uint32_t kNil = 0xFFFFFFFFu;
 constexpr uint32_t kLog0 = PBIT_LOG0;
 // Levels >= 1 walk the list of chains of the level below.
 constexpr uint32_t kLogUp = PBIT_LOGUP;
+// Relink by node ranges: lists of 2^18 .. 2^25 nodes; ranges of 2^14 nodes
+// (2^15 above 2^24 nodes), at most kRelinkRangesMax of them; tiles of
+// kRelinkTile list positions in the bucketing kernel.
+constexpr uint64_t kRelinkMinNodes = 1ull << 18;
+constexpr uint64_t kRelinkMaxNodes = 1ull << 25;
+constexpr uint32_t kRelinkRangesMax = 1024;
+constexpr uint32_t kRelinkTile = 16384;
 // The last level is ranked inside one workgroup's LDS.
 constexpr uint32_t kBaseMax = PBIT_BASEMAX;
 constexpr int kMaxLevels = 12;
@@ -131,6 +138,11 @@ struct Plan {
     LevelPlan lv[kMaxLevels];
     size_t o_header, o_hist, o_dbase, o_look, zero_end;
     size_t o_nodes, o_pairsA, o_pairsB, o_idxA, o_idxB;
+    // relink by node ranges (one list, 2^18 <= n <= 2^25): 2^relink_r nodes
+    // per range; per tile of the bucketing kernel, the first slot of each
+    // range's pairs ([range][tile]); relink_r = 0: the direct scatter
+    uint32_t relink_r, relink_ranges, relink_tiles;
+    size_t o_rstart;
     // many-list sorts
     size_t o_table, o_headbits;     // node -> list, head marks
     size_t o_lseg, o_segl, o_coff;  // list -> segment, segment -> list, segment offsets

@@ -342,6 +342,143 @@ __global__ __launch_bounds__(256) void k_relink(OrderSrc src, uint32_t n,
     }
 }
 
+// Relink by node ranges.  The direct scatter writes each link at a random
+// node, one 4-byte write per node anywhere in next[].  Instead:
+//   1. k_relink_bucket: each tile of kRelinkTile list positions forms its
+//      (node, successor) pairs and groups them in LDS by the node's range
+//      (node >> r), written back over the tile's own span of a pairs buffer,
+//      with the first slot of every range in the tile ([range][tile]);
+//   2. k_relink_ranges: one workgroup per range of 2^r nodes gathers that
+//      range's pairs from every tile into LDS, then writes the range's links
+//      out in node order (coalesced).
+// The result is the same array; the writes to next[] become sequential.
+constexpr int kRelinkThreads = 1024;
+constexpr int kRelinkItems = (int)kRelinkTile / kRelinkThreads;
+
+__global__ __launch_bounds__(kRelinkThreads) void k_relink_bucket(
+    OrderSrc src, uint32_t n, uint32_t r, uint32_t nranges, uint32_t ntiles,
+    uint2* __restrict__ pairsA, uint2* __restrict__ pairsB, uint32_t* __restrict__ rstart,
+    uint32_t* __restrict__ result, const Header* hdr)
+{
+    __shared__ uint32_t s_cnt[kRelinkRangesMax + 1];
+    __shared__ uint32_t s_wsum[kRelinkThreads / 64];
+    __shared__ __attribute__((aligned(16))) uint2 s_pairs[kRelinkTile];
+    const int32_t st = hdr->status;
+    const uint32_t tid = threadIdx.x, t = blockIdx.x;
+    if (st != 0) {
+        if (t == 0 && tid == 0) {
+            result[0] = kNil;
+            result[1] = (uint32_t)st;
+        }
+        return;
+    }
+    const uint32_t kind = hdr->final_kind;
+    // the pairs go to a buffer the order is not read from
+    uint2* pairs = kind == kBufPairsA ? pairsB : pairsA;
+    const uint64_t base = (uint64_t)t * kRelinkTile;
+    const uint32_t cnt = (uint32_t)min<uint64_t>(kRelinkTile, (uint64_t)n - base);
+    for (uint32_t i = tid; i <= kRelinkRangesMax; i += kRelinkThreads)
+        s_cnt[i] = 0;
+    __syncthreads();
+    uint32_t node[kRelinkItems], succ[kRelinkItems], slot[kRelinkItems];
+#pragma unroll
+    for (int i = 0; i < kRelinkItems; i++) {
+        const uint32_t k = (uint32_t)i * kRelinkThreads + tid;
+        node[i] = kNil;
+        succ[i] = kNil;
+        slot[i] = 0;
+        if (k < cnt) {
+            const uint64_t j = base + k;
+            const uint32_t v = order_at(src, kind, j);
+            succ[i] = j + 1 < n ? order_at(src, kind, j + 1) : kNil;
+            if (v < n) {
+                node[i] = v;
+                slot[i] = atomicAdd(&s_cnt[v >> r], 1u);  // any order inside a range
+            }
+        }
+    }
+    __syncthreads();
+    // exclusive scan of the range counts (one entry per thread)
+    const uint32_t lane = tid % 64, wave = tid / 64;
+    const uint32_t v = tid < nranges ? s_cnt[tid] : 0u;
+    uint32_t incl = v;
+#pragma unroll
+    for (uint32_t off = 1; off < 64; off <<= 1) {
+        const uint32_t up = __shfl_up(incl, off, 64);
+        if (lane >= off)
+            incl += up;
+    }
+    if (lane == 63)
+        s_wsum[wave] = incl;
+    __syncthreads();
+    uint32_t wbase = 0;
+    for (uint32_t w = 0; w < wave; w++)
+        wbase += s_wsum[w];
+    __syncthreads();
+    if (tid < nranges)
+        s_cnt[tid] = wbase + incl - v;
+    if (tid == 0)
+        s_cnt[nranges] = cnt;
+    __syncthreads();
+    for (uint32_t b = tid; b <= nranges; b += kRelinkThreads)
+        rstart[(size_t)b * ntiles + t] = s_cnt[b];
+#pragma unroll
+    for (int i = 0; i < kRelinkItems; i++)
+        if (node[i] != kNil)
+            s_pairs[s_cnt[node[i] >> r] + slot[i]] = make_uint2(node[i], succ[i]);
+    __syncthreads();
+    for (uint32_t k = tid; k < cnt; k += kRelinkThreads)
+        pairs[base + k] = s_pairs[k];
+    if (t == 0 && tid == 0) {
+        result[0] = order_at(src, kind, 0);
+        result[1] = 0;
+    }
+}
+
+// One workgroup per range of R nodes: every tile's pairs of this range (a
+// segment of about kRelinkTile / ranges pairs per tile, read 8 pairs at a
+// time, several tiles per thread) land in LDS at their node; then the range's
+// links are written in node order.
+template <int R>
+__global__ __launch_bounds__(kRelinkThreads) void k_relink_ranges(
+    const uint2* __restrict__ pairsA, const uint2* __restrict__ pairsB,
+    const uint32_t* __restrict__ rstart, uint32_t n, uint32_t ntiles,
+    char* __restrict__ out_base, uint64_t out_stride, const Header* hdr)
+{
+    __shared__ uint32_t s_next[R];
+    if (hdr->status != 0)
+        return;
+    const uint2* pairs = hdr->final_kind == kBufPairsA ? pairsB : pairsA;
+    const uint32_t b = blockIdx.x, tid = threadIdx.x;
+    const uint64_t lo = (uint64_t)b * R;
+    const uint32_t len = (uint32_t)min<uint64_t>(R, (uint64_t)n - lo);
+    const uint32_t* s0 = rstart + (size_t)b * ntiles;
+    const uint32_t* s1 = rstart + (size_t)(b + 1) * ntiles;
+    for (uint32_t t = tid; t < ntiles; t += kRelinkThreads) {
+        const uint32_t a = t < ntiles ? s0[t] : 0u;
+        const uint32_t e = t < ntiles ? min(s1[t], kRelinkTile) : 0u;
+        const uint2* p = pairs + (uint64_t)t * kRelinkTile;
+        for (uint32_t k0 = a; k0 < e; k0 += 8) {
+            uint2 q[8];
+#pragma unroll
+            for (uint32_t u = 0; u < 8; u++)
+                if (k0 + u < e)
+                    q[u] = p[k0 + u];
+#pragma unroll
+            for (uint32_t u = 0; u < 8; u++) {
+                if (k0 + u < e) {
+                    const uint32_t loc = q[u].x - (uint32_t)lo;
+                    if (loc < len)
+                        s_next[loc] = q[u].y;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < len; i += kRelinkThreads)
+        *(uint32_t*)(out_base + (lo + i) * out_stride) = s_next[i];
+}
+
 __global__ void k_empty_result(uint32_t* result)
 {
     result[0] = kNil;
@@ -560,8 +697,29 @@ static hipError_t enqueue_after_pack(const Plan& P, uint32_t head, char* out_bas
         uint32_t blocks = (uint32_t)((P.n + 255) / 256);
         mark(prof, s, kStageRelink);
         const OrderSrc src = P.key_bytes == 8 ? order_src<uint64_t>(P, ws) : order_src<uint32_t>(P, ws);
-        hipLaunchKernelGGL(k_relink, dim3(blocks), dim3(256), 0, s, src, (uint32_t)P.n, out_base,
-                           out_stride, d_result, (const Header*)hdr);
+        if (P.relink_r != 0) {
+            hipLaunchKernelGGL(k_relink_bucket, dim3(P.relink_tiles), dim3(kRelinkThreads), 0, s,
+                               src, (uint32_t)P.n, P.relink_r, P.relink_ranges, P.relink_tiles,
+                               (uint2*)(ws + P.o_pairsA), (uint2*)(ws + P.o_pairsB),
+                               (uint32_t*)(ws + P.o_rstart), d_result, (const Header*)hdr);
+            if ((e = hipGetLastError()) != hipSuccess)
+                return e;
+            if (P.relink_r == 14)
+                hipLaunchKernelGGL((k_relink_ranges<1 << 14>), dim3(P.relink_ranges),
+                                   dim3(kRelinkThreads), 0, s, (const uint2*)(ws + P.o_pairsA),
+                                   (const uint2*)(ws + P.o_pairsB),
+                                   (const uint32_t*)(ws + P.o_rstart), (uint32_t)P.n,
+                                   P.relink_tiles, out_base, out_stride, (const Header*)hdr);
+            else
+                hipLaunchKernelGGL((k_relink_ranges<1 << 15>), dim3(P.relink_ranges),
+                                   dim3(kRelinkThreads), 0, s, (const uint2*)(ws + P.o_pairsA),
+                                   (const uint2*)(ws + P.o_pairsB),
+                                   (const uint32_t*)(ws + P.o_rstart), (uint32_t)P.n,
+                                   P.relink_tiles, out_base, out_stride, (const Header*)hdr);
+        } else {
+            hipLaunchKernelGGL(k_relink, dim3(blocks), dim3(256), 0, s, src, (uint32_t)P.n,
+                               out_base, out_stride, d_result, (const Header*)hdr);
+        }
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }
