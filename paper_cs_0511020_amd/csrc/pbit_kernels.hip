@@ -436,9 +436,10 @@ __global__ __launch_bounds__(kRelinkThreads) void k_relink_bucket(
 }
 
 // One workgroup per range of R nodes: every tile's pairs of this range (a
-// segment of about kRelinkTile / ranges pairs per tile, read 8 pairs at a
-// time, several tiles per thread) land in LDS at their node; then the range's
-// links are written in node order.
+// segment of about kRelinkTile / ranges pairs per tile, read kRelinkBlock
+// pairs at a time, one or two tiles per thread) land in LDS at their node;
+// then the range's links are written in node order.
+constexpr uint32_t kRelinkBlock = 16;
 template <int R>
 __global__ __launch_bounds__(kRelinkThreads) void k_relink_ranges(
     const uint2* __restrict__ pairsA, const uint2* __restrict__ pairsB,
@@ -458,14 +459,14 @@ __global__ __launch_bounds__(kRelinkThreads) void k_relink_ranges(
         const uint32_t a = t < ntiles ? s0[t] : 0u;
         const uint32_t e = t < ntiles ? min(s1[t], kRelinkTile) : 0u;
         const uint2* p = pairs + (uint64_t)t * kRelinkTile;
-        for (uint32_t k0 = a; k0 < e; k0 += 8) {
-            uint2 q[8];
+        for (uint32_t k0 = a; k0 < e; k0 += kRelinkBlock) {
+            uint2 q[kRelinkBlock];
 #pragma unroll
-            for (uint32_t u = 0; u < 8; u++)
+            for (uint32_t u = 0; u < kRelinkBlock; u++)
                 if (k0 + u < e)
                     q[u] = p[k0 + u];
 #pragma unroll
-            for (uint32_t u = 0; u < 8; u++) {
+            for (uint32_t u = 0; u < kRelinkBlock; u++) {
                 if (k0 + u < e) {
                     const uint32_t loc = q[u].x - (uint32_t)lo;
                     if (loc < len)
