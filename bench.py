@@ -253,8 +253,7 @@ def run_plain(args, lib, torch, np, inputs, bytemodel, EventPool):
         ex2 = ln2.get("digit_pass", M // K2)
         pass2 = st2.get("digit_pass", 0.0) / max(ex2, 1)
         w2 = M // 8
-        pb2 = (bytemodel.kernel_bytes_per_node("digit_pass", w2) * (ex2 - 1)
-               + bytemodel.kernel_bytes_per_node("digit_pass", w2, last_pass=True)) / ex2
+        pb2 = bytemodel.digit_pass_bytes_per_node(w2, ex2, n, K2)
         other = {"K": K2, "p50_ms": round(statistics.median(lat2), 4),
                  "Mnodes_s_at_p50": round(n / (statistics.median(lat2) * 1e-3) / 1e6, 1),
                  "digit_passes": ex2, "digit_pass_ms": round(pass2, 5),
@@ -324,8 +323,7 @@ def run_plain(args, lib, torch, np, inputs, bytemodel, EventPool):
     def stage_roofline(st):
         launch_ms = stage_ms[st] / launches[st]
         if st == "digit_pass":
-            per_node = (bytemodel.kernel_bytes_per_node(st, w) * (executed - 1)
-                        + bytemodel.kernel_bytes_per_node(st, w, last_pass=True)) / executed
+            per_node = bytemodel.digit_pass_bytes_per_node(w, executed, n, Keff)
         else:
             per_node = bytemodel.kernel_bytes_per_node(st, w)
         nbytes = per_node * n

@@ -13,7 +13,11 @@ Two models are kept apart:
 
 * ``kernel_bytes_per_node`` counts, for one kernel of this implementation,
   the element bytes it reads and writes once each; a kernel's roofline uses
-  it with the number of nodes one launch processes.
+  it with the number of nodes one launch processes.  A digit pass reads and
+  writes (key, index) pairs, except that the last pass writes indices only
+  and, when node indices fit below one K-bit digit in 32 bits, the pass
+  before it writes one 4-byte word (the last pass's digit over the index)
+  that the last pass reads.
 """
 from __future__ import annotations
 
@@ -34,7 +38,8 @@ def path_bytes_per_node(w: int, passes: int) -> int:
     return 28 + 3 * w + (passes - 1) * (2 * w + 8)
 
 
-def kernel_bytes_per_node(stage: str, w: int, last_pass: bool = False) -> int:
+def kernel_bytes_per_node(stage: str, w: int, last_pass: bool = False,
+                          packed_in: bool = False, packed_out: bool = False) -> int:
     if stage == "pack":
         return 4 + w + record_bytes(w)
     if stage == "walk0":
@@ -42,7 +47,30 @@ def kernel_bytes_per_node(stage: str, w: int, last_pass: bool = False) -> int:
     if stage == "unchain":
         return entry_bytes(w) + w + 4
     if stage == "digit_pass":
-        return (w + 4) + (4 if last_pass else w + 4)
+        return (4 if packed_in else w + 4) + (4 if last_pass or packed_out else w + 4)
     if stage == "relink":
         return 8
     raise KeyError(stage)
+
+
+def packs_last_pass(n: int, K: int, executed: int) -> bool:
+    """Whether the last two executed passes of one list exchange packed words:
+    node indices (below n) must fit in 32 - K bits."""
+    return executed >= 2 and n <= (1 << (32 - K))
+
+
+def digit_pass_bytes_per_node(w: int, executed: int, n: int, K: int) -> float:
+    """Mean element bytes per node of one digit-pass launch over a sort's
+    executed passes (one list)."""
+    if executed <= 0:
+        return 0.0
+    if executed == 1:
+        return float(kernel_bytes_per_node("digit_pass", w, last_pass=True))
+    if packs_last_pass(n, K, executed):
+        total = (kernel_bytes_per_node("digit_pass", w) * (executed - 2)
+                 + kernel_bytes_per_node("digit_pass", w, packed_out=True)
+                 + kernel_bytes_per_node("digit_pass", w, last_pass=True, packed_in=True))
+    else:
+        total = (kernel_bytes_per_node("digit_pass", w) * (executed - 1)
+                 + kernel_bytes_per_node("digit_pass", w, last_pass=True))
+    return total / executed

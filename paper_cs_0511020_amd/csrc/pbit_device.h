@@ -501,18 +501,34 @@ __global__ __launch_bounds__(256) void k_unchain(const uint2* __restrict__ chain
 // Buffers of each pass: the list order starts as (key, node) pairs A; passes
 // go pairs to pairs in ping-pong, and the last pass that runs writes node
 // indices only.  Skipped passes (the identity) leave the buffers as they are.
-__device__ __forceinline__ void assign_kinds(const uint32_t* skip, uint32_t passes, Header* hdr)
+// The last pass needs only its own digit of each key (the patterns below it
+// are already in the order, those above it are constant), so with `packable`
+// (node indices below 2^(32 - rb)) the pass before it writes one word per
+// element, that digit over the node index, instead of a pair.
+__device__ __forceinline__ void assign_kinds(const uint32_t* skip, uint32_t passes, Header* hdr,
+                                             bool packable = false, uint32_t rb = 0)
 {
-    int last = -1;
+    int last = -1, prev = -1;
     for (uint32_t p = 0; p < passes; p++)
-        if (!skip[p])
+        if (!skip[p]) {
+            prev = last;
             last = (int)p;
+        }
+    const bool packed = packable && prev >= 0;
     uint32_t cur = kBufPairsA;
     for (uint32_t p = 0; p < passes; p++) {
         PassSched ps = hdr->sched[p];
         ps.skip = skip[p];
         ps.in_kind = cur;
-        ps.out_kind = (int)p == last ? kBufIdxA : (cur == kBufPairsA ? kBufPairsB : kBufPairsA);
+        ps.pk_shift = 0;
+        if ((int)p == last) {
+            ps.out_kind = kBufIdxA;
+        } else if (packed && (int)p == prev) {
+            ps.out_kind = cur == kBufPairsA ? kBufPackB : kBufPackA;
+            ps.pk_shift = (uint32_t)last * rb;
+        } else {
+            ps.out_kind = cur == kBufPairsA ? kBufPairsB : kBufPairsA;
+        }
         if (!ps.skip)
             cur = ps.out_kind;
         hdr->sched[p] = ps;
@@ -560,8 +576,10 @@ __device__ __forceinline__ void schedule_body(const uint32_t* __restrict__ hist,
             dbase[p * radix + tid] = s_v[tid];
         __syncthreads();
     }
-    if (tid == 0)
-        assign_kinds(s_skip, passes, hdr);
+    if (tid == 0) {
+        const uint32_t rb = 31u - (uint32_t)__clz(radix);
+        assign_kinds(s_skip, passes, hdr, (uint64_t)n <= (1ull << (32 - rb)), rb);
+    }
 }
 
 template <int RB>
@@ -673,9 +691,15 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
     const uint32_t n = SEG ? hdr->seg_nodes : n_all;
     const uint32_t nseg = SEG ? hdr->n_segs : 0u;
     const bool out_pairs = ps.out_kind < kBufIdxA;
+    const bool out_packed = ps.out_kind >= kBufPackA;
+    const bool in_packed = ps.in_kind >= kBufPackA;
     const Pair<KeyT>* pin = ps.in_kind == kBufPairsB ? pairsB : pairsA;
     Pair<KeyT>* pout = ps.out_kind == kBufPairsB ? pairsB : pairsA;
     uint32_t* iout = ps.out_kind == kBufIdxB ? idxB : idxA;
+    // packed words: digit in the top RB bits, node index below
+    constexpr uint32_t PK = 32u - RB;
+    const uint32_t* uin = (const uint32_t*)(ps.in_kind == kBufPackB ? pairsB : pairsA);
+    uint32_t* uout = (uint32_t*)(ps.out_kind == kBufPackB ? pairsB : pairsA);
 
     const uint32_t tid = threadIdx.x;
     const uint32_t wave = tid / 64, lane = tid % 64;
@@ -711,24 +735,42 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
 
     KeyT key[ITEMS];
     uint32_t idx[ITEMS], dig[ITEMS], rank[ITEMS];
+    if (!SEG && in_packed) {
+        // the key is only needed for this pass's digit: it is kept in place
 #pragma unroll
-    for (int i = 0; i < ITEMS; i++) {
-        const uint64_t e = wbase + (uint64_t)i * 64 + lane;
-        if (e < n) {
-            const Pair<KeyT> v = pin[e];
-            key[i] = pair_key<KeyT>(v);
-            idx[i] = v.idx;
-            dig[i] = (uint32_t)(key[i] >> shift) & (RADIX - 1u);
-            if constexpr (SEG) {
-                uint32_t sl = 0;
-                while (sl < nb && s_bound[sl] <= (uint32_t)e)
-                    sl++;
-                dig[i] |= sl << 9;
+        for (int i = 0; i < ITEMS; i++) {
+            const uint64_t e = wbase + (uint64_t)i * 64 + lane;
+            if (e < n) {
+                const uint32_t v = uin[e];
+                dig[i] = v >> PK;
+                idx[i] = v & ((1u << PK) - 1u);
+                key[i] = (KeyT)((KeyT)dig[i] << shift);
+            } else {
+                key[i] = 0;
+                idx[i] = 0;
+                dig[i] = RADIX;
             }
-        } else {
-            key[i] = 0;
-            idx[i] = 0;
-            dig[i] = RADIX;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++) {
+            const uint64_t e = wbase + (uint64_t)i * 64 + lane;
+            if (e < n) {
+                const Pair<KeyT> v = pin[e];
+                key[i] = pair_key<KeyT>(v);
+                idx[i] = v.idx;
+                dig[i] = (uint32_t)(key[i] >> shift) & (RADIX - 1u);
+                if constexpr (SEG) {
+                    uint32_t sl = 0;
+                    while (sl < nb && s_bound[sl] <= (uint32_t)e)
+                        sl++;
+                    dig[i] |= sl << 9;
+                }
+            } else {
+                key[i] = 0;
+                idx[i] = 0;
+                dig[i] = RADIX;
+            }
         }
     }
     // dig[i] bits: 0..8 digit (RADIX = invalid), 9..15 segment slot (SEG),
@@ -876,8 +918,13 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
                 const uint64_t b0 = (uint64_t)j * TILE;
                 const uint64_t b1 = min<uint64_t>(b0 + TILE, (uint64_t)n);
                 uint32_t c = 0;
-                for (uint64_t q = b0; q < b1; q++)
-                    c += ((uint32_t)(pair_key<KeyT>(pin[q]) >> shift) & (RADIX - 1u)) == d;
+                if (!SEG && in_packed) {
+                    for (uint64_t q = b0; q < b1; q++)
+                        c += (uin[q] >> PK) == d;
+                } else {
+                    for (uint64_t q = b0; q < b1; q++)
+                        c += ((uint32_t)(pair_key<KeyT>(pin[q]) >> shift) & (RADIX - 1u)) == d;
+                }
                 excl += c;
                 j--;
                 spins = 0;
@@ -923,6 +970,8 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
             if (g < n) {
                 if (out_pairs)
                     pout[g] = make_pair_kv<KeyT>(kv.key, kv.idx);
+                else if (!SEG && out_packed)
+                    uout[g] = (((uint32_t)(kv.key >> ps.pk_shift) & (RADIX - 1u)) << PK) | kv.idx;
                 else
                     iout[g] = kv.idx;
             }

@@ -64,14 +64,19 @@ constexpr uint32_t kFlagPrefix = 2u << 30;
 constexpr uint32_t kCountMask = (1u << 30) - 1u;
 
 // List-order buffers: (key, node) pairs while passes remain, node indices
-// alone after the last pass.
-enum BufKind : uint32_t { kBufPairsA = 0, kBufPairsB = 1, kBufIdxA = 2, kBufIdxB = 3 };
+// alone after the last pass.  Packed: one 32-bit word per element, the last
+// pass's digit in the top K bits over the node index (in the memory of pairs
+// A or B), written by the last pass but one when the index fits 32 - K bits.
+enum BufKind : uint32_t {
+    kBufPairsA = 0, kBufPairsB = 1, kBufIdxA = 2, kBufIdxB = 3, kBufPackA = 4, kBufPackB = 5
+};
 
 struct PassSched {
     uint32_t skip;      // every element has the same digit: the pass is the identity
     uint32_t in_kind;   // BufKind read
     uint32_t out_kind;  // BufKind written
     uint32_t ballot;    // rank by ballots (one digit holds over 1/16 of the elements)
+    uint32_t pk_shift;  // out_kind packed: bit position of the digit the word carries
 };
 
 // Device-side header at the start of the workspace (zeroed per sort).

@@ -40,3 +40,21 @@ def test_kernel_bytes_per_node():
     assert bytemodel.kernel_bytes_per_node("digit_pass", 8) == 24
     with pytest.raises(KeyError):
         bytemodel.kernel_bytes_per_node("nonesuch", 4)
+
+
+def test_packed_digit_passes():
+    # the pass before the last writes one 4-byte word per node, which the last
+    # pass reads: u32 keys, K = 8, four passes at 2^24 nodes move
+    # 16 + 16 + (8 + 4) + (4 + 4) bytes per node
+    assert bytemodel.kernel_bytes_per_node("digit_pass", 4, packed_out=True) == 12
+    assert bytemodel.kernel_bytes_per_node("digit_pass", 4, last_pass=True, packed_in=True) == 8
+    assert bytemodel.digit_pass_bytes_per_node(4, 4, 1 << 24, 8) == (16 + 16 + 12 + 8) / 4
+    # one node more and the indices no longer fit below an 8-bit digit
+    assert not bytemodel.packs_last_pass((1 << 24) + 1, 8, 4)
+    assert bytemodel.digit_pass_bytes_per_node(4, 4, (1 << 24) + 1, 8) == (16 * 3 + 12) / 4
+    # 4-bit digits pack up to 2^28 nodes; u64 pairs are 12 bytes
+    assert bytemodel.packs_last_pass(1 << 28, 4, 16)
+    assert bytemodel.digit_pass_bytes_per_node(8, 8, 1 << 20, 8) == (24 * 6 + 16 + 8) / 8
+    # a single executed pass reads pairs and writes indices
+    assert bytemodel.digit_pass_bytes_per_node(4, 1, 1000, 8) == 12
+    assert bytemodel.digit_pass_bytes_per_node(4, 0, 1000, 8) == 0
