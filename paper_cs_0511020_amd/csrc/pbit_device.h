@@ -441,9 +441,10 @@ __global__ __launch_bounds__(256) void k_unchain(const uint2* __restrict__ chain
     constexpr uint32_t PER = UnchainPer<KeyT>::value;
     // threads per chain: together they copy the mean chain length per step
     constexpr uint32_t G = kUnchainThreads / PER;
-    if (hdr->status != 0)
-        return;
+    static_assert(kUnchainThreads <= kPlane, "a chain's first copy round lies in its first plane");
     if (blockIdx.x < kLongBlocks) {
+        if (hdr->status != 0)
+            return;
         const uint32_t listed = min(hdr->n_long, kLongListMax);
         const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
         if (i < listed) {
@@ -460,29 +461,39 @@ __global__ __launch_bounds__(256) void k_unchain(const uint2* __restrict__ chain
     const uint32_t c = (uint32_t)(g / G);
     if (c >= n_chains)
         return;
-    const uint32_t full = chain_rec[c].y;
-    const uint32_t len = min(full, cap);
-    const uint32_t base = offn_chain[c];
     const uint32_t lead = (uint32_t)(g % G);
+    const uint32_t t0 = lead * PER;
+    // the chain's record, its offset and its first entries are loaded
+    // together, before the status is known: every chain's slot holds its
+    // first plane, so the addresses are valid whatever was stored there
+    const int32_t st = hdr->status;
+    const uint2 cr = chain_rec[c];
+    const uint32_t base = offn_chain[c];
+    uint4 v0[PER > 1 ? PER / 2 : 1];
+    Entry<KeyT> e0;
+    if constexpr (PER > 1) {
+        const uint4* src = (const uint4*)&ent[ent_at(n_chains, c, t0)];
+#pragma unroll
+        for (uint32_t h = 0; h < PER / 2; h++)
+            v0[h] = src[h];
+    } else {
+        e0 = ent[ent_at(n_chains, c, t0)];
+    }
+    if (st != 0)
+        return;
+    const uint32_t full = cr.y;
+    const uint32_t len = min(full, cap);
     if (lead == 0 && full > cap) {
         const uint32_t own = resume[c];
         if (own != kNil)
             walk_rest<KeyT>(nodes, own, (uint64_t)base + cap,
                             min<uint64_t>((uint64_t)base + full, (uint64_t)n), n, out);
     }
-
-    for (uint32_t t = lead * PER; t < len; t += kUnchainThreads) {
+    // entries t .. t + PER - 1 (adjacent in one plane, t a multiple of PER)
+    // to list positions base + t ..
+    auto put = [&](uint32_t t, const uint4* v, const Entry<KeyT>& e) {
         const uint32_t pos = base + t;
-        if (pos >= n)
-            break;
         if constexpr (PER > 1) {
-            // t is a multiple of PER, so entries t .. t + PER - 1 are adjacent
-            // in one plane: PER / 2 aligned 16-byte loads
-            const uint4* src = (const uint4*)&ent[ent_at(n_chains, c, t)];
-            uint4 v[PER / 2];
-#pragma unroll
-            for (uint32_t h = 0; h < PER / 2; h++)
-                v[h] = src[h];
 #pragma unroll
             for (uint32_t j = 0; j < PER; j++) {
                 const uint4 w = v[j / 2];
@@ -491,9 +502,26 @@ __global__ __launch_bounds__(256) void k_unchain(const uint2* __restrict__ chain
                     out[pos + j] = make_pair_kv<KeyT>((KeyT)key, idx);
             }
         } else {
-            const Entry<KeyT> e = ent[ent_at(n_chains, c, t)];
             out[pos] = make_pair_kv<KeyT>(entry_key<KeyT>(e), e.idx);
         }
+    };
+    if (t0 >= len || base + t0 >= n)
+        return;
+    put(t0, v0, e0);
+    for (uint32_t t = t0 + kUnchainThreads; t < len; t += kUnchainThreads) {
+        if (base + t >= n)
+            break;
+        uint4 v[PER > 1 ? PER / 2 : 1];
+        Entry<KeyT> e;
+        if constexpr (PER > 1) {
+            const uint4* src = (const uint4*)&ent[ent_at(n_chains, c, t)];
+#pragma unroll
+            for (uint32_t h = 0; h < PER / 2; h++)
+                v[h] = src[h];
+        } else {
+            e = ent[ent_at(n_chains, c, t)];
+        }
+        put(t, v, e);
     }
 }
 
