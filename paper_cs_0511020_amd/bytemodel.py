@@ -61,16 +61,26 @@ def packs_last_pass(n: int, K: int, executed: int) -> bool:
 
 def digit_pass_bytes_per_node(w: int, executed: int, n: int, K: int) -> float:
     """Mean element bytes per node of one digit-pass launch over a sort's
-    executed passes (one list)."""
+    executed passes (one list, no pattern skipped).  With 64-bit keys the
+    passes over the high 32 bits move (high half, index) pairs of 8 bytes,
+    which the last pass over the low half writes."""
     if executed <= 0:
         return 0.0
-    if executed == 1:
-        return float(kernel_bytes_per_node("digit_pass", w, last_pass=True))
-    if packs_last_pass(n, K, executed):
-        total = (kernel_bytes_per_node("digit_pass", w) * (executed - 2)
-                 + kernel_bytes_per_node("digit_pass", w, packed_out=True)
-                 + kernel_bytes_per_node("digit_pass", w, last_pass=True, packed_in=True))
-    else:
-        total = (kernel_bytes_per_node("digit_pass", w) * (executed - 1)
-                 + kernel_bytes_per_node("digit_pass", w, last_pass=True))
+    pair = w + 4
+    packed = packs_last_pass(n, K, executed)
+    hi_from = executed // 2 if w == 8 else executed
+    total = 0
+    for p in range(executed):
+        rd = 8 if p >= hi_from and p > 0 else pair
+        if p == executed - 1:
+            wr = 4
+            if packed:
+                rd = 4
+        elif packed and p == executed - 2:
+            wr = 4
+        elif p + 1 >= hi_from:
+            wr = 8
+        else:
+            wr = pair
+        total += rd + wr
     return total / executed

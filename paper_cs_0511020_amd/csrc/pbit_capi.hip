@@ -144,6 +144,11 @@ static bool plan_common(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, size
     P->key_bytes = M / 8;
     P->tile = pass_tile(P->key_bytes, P->RB);
     P->tiles = (uint32_t)ceil_div(n ? n : 1, P->tile);
+    // the passes over the high half of one list's 64-bit keys (set by the
+    // single-list planner) use the 32-bit shape
+    P->hi_from = P->passes;
+    P->tiles_hi = (uint32_t)ceil_div(n ? n : 1, pass_tile(4, P->RB));
+    P->look_tiles = P->key_bytes == 8 ? (P->tiles > P->tiles_hi ? P->tiles : P->tiles_hi) : P->tiles;
     off = 0;
     P->o_header = off;
     off = align_up(off + sizeof(Header));
@@ -152,7 +157,7 @@ static bool plan_common(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, size
     P->o_dbase = off;
     off = align_up(off + (size_t)P->passes * P->radix * 4);
     P->o_look = off;
-    off = align_up(off + (size_t)P->passes * P->tiles * P->radix * lw_bytes);
+    off = align_up(off + (size_t)P->passes * P->look_tiles * P->radix * lw_bytes);
     P->o_lcnt = off;
     off = align_up(off + lcnt_bytes);
     P->zero_end = off;
@@ -210,6 +215,8 @@ bool make_plan(uint64_t n, uint32_t M, uint32_t K, uint32_t flags, Plan* P)
     size_t off = 0;
     if (!plan_common(n, M, K, flags, lw_bytes, 1 + ceil_div(n, 1ull << kLog0), cap, 0, P, off))
         return false;
+    if (P->key_bytes == 8)
+        P->hi_from = P->passes / 2;
     int k = 1;
     uint64_t m = P->lv[0].n_static;
     while (m > kBaseMax) {

@@ -532,9 +532,13 @@ __global__ __launch_bounds__(256) void k_unchain(const uint2* __restrict__ chain
 // The last pass needs only its own digit of each key (the patterns below it
 // are already in the order, those above it are constant), so with `packable`
 // (node indices below 2^(32 - rb)) the pass before it writes one word per
-// element, that digit over the node index, instead of a pair.
+// element, that digit over the node index, instead of a pair.  For one list
+// of 64-bit keys, passes from `hi_from` on (the high 32 key bits) run as
+// 32-bit-key passes over (high half, node) pairs, which the last running
+// pass before them writes.
 __device__ __forceinline__ void assign_kinds(const uint32_t* skip, uint32_t passes, Header* hdr,
-                                             bool packable = false, uint32_t rb = 0)
+                                             bool packable = false, uint32_t rb = 0,
+                                             uint32_t hi_from = kMaxPasses)
 {
     int last = -1, prev = -1;
     for (uint32_t p = 0; p < passes; p++)
@@ -549,13 +553,23 @@ __device__ __forceinline__ void assign_kinds(const uint32_t* skip, uint32_t pass
         ps.skip = skip[p];
         ps.in_kind = cur;
         ps.pk_shift = 0;
+        // the next pass that runs after p
+        int next = -1;
+        for (uint32_t q = p + 1; q < passes && next < 0; q++)
+            if (!skip[q])
+                next = (int)q;
+        const bool b = !buf_in_b(cur);  // the other buffer
         if ((int)p == last) {
             ps.out_kind = kBufIdxA;
         } else if (packed && (int)p == prev) {
-            ps.out_kind = cur == kBufPairsA ? kBufPackB : kBufPackA;
-            ps.pk_shift = (uint32_t)last * rb;
+            ps.out_kind = b ? kBufPackB : kBufPackA;
+            // the digit's bit position in the writer's own key (a high-half
+            // pass holds key bits 32.. only)
+            ps.pk_shift = (uint32_t)last * rb - (p >= hi_from ? 32u : 0u);
+        } else if (next >= (int)hi_from) {
+            ps.out_kind = b ? kBufHalfB : kBufHalfA;
         } else {
-            ps.out_kind = cur == kBufPairsA ? kBufPairsB : kBufPairsA;
+            ps.out_kind = b ? kBufPairsB : kBufPairsA;
         }
         if (!ps.skip)
             cur = ps.out_kind;
@@ -571,7 +585,8 @@ __device__ __forceinline__ void assign_kinds(const uint32_t* skip, uint32_t pass
 // radix <= 256): one extra block of the level-0 walk.
 __device__ __forceinline__ void schedule_body(const uint32_t* __restrict__ hist,
                                               uint32_t* __restrict__ dbase, uint32_t passes,
-                                              uint32_t n, uint32_t radix, Header* hdr)
+                                              uint32_t n, uint32_t radix, Header* hdr,
+                                              uint32_t hi_from)
 {
     __shared__ uint32_t s_v[256];
     __shared__ uint32_t s_skip[kMaxPasses];
@@ -606,16 +621,16 @@ __device__ __forceinline__ void schedule_body(const uint32_t* __restrict__ hist,
     }
     if (tid == 0) {
         const uint32_t rb = 31u - (uint32_t)__clz(radix);
-        assign_kinds(s_skip, passes, hdr, (uint64_t)n <= (1ull << (32 - rb)), rb);
+        assign_kinds(s_skip, passes, hdr, (uint64_t)n <= (1ull << (32 - rb)), rb, hi_from);
     }
 }
 
 template <int RB>
 __global__ __launch_bounds__(256) void k_schedule(const uint32_t* __restrict__ hist,
                                                   uint32_t* __restrict__ dbase, uint32_t passes,
-                                                  uint32_t n, Header* hdr)
+                                                  uint32_t n, Header* hdr, uint32_t hi_from)
 {
-    schedule_body(hist, dbase, passes, n, 1u << RB, hdr);
+    schedule_body(hist, dbase, passes, n, 1u << RB, hdr, hi_from);
 }
 
 // ---------------------------------------------------------------- segments
@@ -685,7 +700,10 @@ template <typename SKey> struct KV { SKey key; uint32_t idx; };
 #endif
 constexpr uint32_t kLookWindow = PBIT_LOOK_WINDOW;
 
-template <typename KeyT, int RB, int BLOCK, int ITEMS, typename LW, bool SEG>
+// HI: a pass over the high 32 bits of one list's 64-bit keys, run as a
+// 32-bit-key pass (KeyT = uint32_t, `shift` relative to bit 32); its input may
+// still be the full (key, node) pairs when no pass over the low half ran.
+template <typename KeyT, int RB, int BLOCK, int ITEMS, typename LW, bool SEG, bool HI = false>
 __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_pass(
     uint32_t pass, uint32_t shift, uint32_t n_all, Pair<KeyT>* __restrict__ pairsA,
     Pair<KeyT>* __restrict__ pairsB, uint32_t* __restrict__ idxA, uint32_t* __restrict__ idxB,
@@ -718,16 +736,25 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
     // the passes, known on the device only
     const uint32_t n = SEG ? hdr->seg_nodes : n_all;
     const uint32_t nseg = SEG ? hdr->n_segs : 0u;
-    const bool out_pairs = ps.out_kind < kBufIdxA;
-    const bool out_packed = ps.out_kind >= kBufPackA;
-    const bool in_packed = ps.in_kind >= kBufPackA;
-    const Pair<KeyT>* pin = ps.in_kind == kBufPairsB ? pairsB : pairsA;
-    Pair<KeyT>* pout = ps.out_kind == kBufPairsB ? pairsB : pairsA;
+    static_assert(!HI || (sizeof(KeyT) == 4 && !SEG), "high-half passes are 32-bit, one list");
+    // this kernel's own pairs: Pair<KeyT>, or (HI) the half pairs
+    const bool out_pairs = HI ? buf_half(ps.out_kind) : buf_pairs(ps.out_kind);
+    const bool out_packed = buf_packed(ps.out_kind);
+    // (64-bit keys) pairs over the high half for the passes that follow
+    const bool out_half = !HI && sizeof(KeyT) == 8 && !SEG && buf_half(ps.out_kind);
+    const bool in_packed = buf_packed(ps.in_kind);
+    // (HI) the full 64-bit pairs, read for their high half
+    const bool in_wide = HI && buf_pairs(ps.in_kind);
+    const bool in_b = buf_in_b(ps.in_kind), out_b = buf_in_b(ps.out_kind);
+    const Pair<KeyT>* pin = in_b ? pairsB : pairsA;
+    Pair<KeyT>* pout = out_b ? pairsB : pairsA;
     uint32_t* iout = ps.out_kind == kBufIdxB ? idxB : idxA;
     // packed words: digit in the top RB bits, node index below
     constexpr uint32_t PK = 32u - RB;
-    const uint32_t* uin = (const uint32_t*)(ps.in_kind == kBufPackB ? pairsB : pairsA);
-    uint32_t* uout = (uint32_t*)(ps.out_kind == kBufPackB ? pairsB : pairsA);
+    const uint32_t* uin = (const uint32_t*)pin;
+    uint32_t* uout = (uint32_t*)pout;
+    const Pair<uint64_t>* win = (const Pair<uint64_t>*)pin;
+    Pair<uint32_t>* hout = (Pair<uint32_t>*)pout;
 
     const uint32_t tid = threadIdx.x;
     const uint32_t wave = tid / 64, lane = tid % 64;
@@ -773,6 +800,21 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
                 dig[i] = v >> PK;
                 idx[i] = v & ((1u << PK) - 1u);
                 key[i] = (KeyT)((KeyT)dig[i] << shift);
+            } else {
+                key[i] = 0;
+                idx[i] = 0;
+                dig[i] = RADIX;
+            }
+        }
+    } else if (HI && in_wide) {
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++) {
+            const uint64_t e = wbase + (uint64_t)i * 64 + lane;
+            if (e < n) {
+                const Pair<uint64_t> v = win[e];
+                key[i] = (KeyT)v.khi;
+                idx[i] = v.idx;
+                dig[i] = (uint32_t)(key[i] >> shift) & (RADIX - 1u);
             } else {
                 key[i] = 0;
                 idx[i] = 0;
@@ -949,6 +991,9 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
                 if (!SEG && in_packed) {
                     for (uint64_t q = b0; q < b1; q++)
                         c += (uin[q] >> PK) == d;
+                } else if (HI && in_wide) {
+                    for (uint64_t q = b0; q < b1; q++)
+                        c += ((win[q].khi >> shift) & (RADIX - 1u)) == d;
                 } else {
                     for (uint64_t q = b0; q < b1; q++)
                         c += ((uint32_t)(pair_key<KeyT>(pin[q]) >> shift) & (RADIX - 1u)) == d;
@@ -998,6 +1043,8 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
             if (g < n) {
                 if (out_pairs)
                     pout[g] = make_pair_kv<KeyT>(kv.key, kv.idx);
+                else if (out_half)
+                    hout[g] = make_pair_kv<uint32_t>((uint32_t)((uint64_t)kv.key >> 32), kv.idx);
                 else if (!SEG && out_packed)
                     uout[g] = (((uint32_t)(kv.key >> ps.pk_shift) & (RADIX - 1u)) << PK) | kv.idx;
                 else

@@ -67,9 +67,20 @@ constexpr uint32_t kCountMask = (1u << 30) - 1u;
 // alone after the last pass.  Packed: one 32-bit word per element, the last
 // pass's digit in the top K bits over the node index (in the memory of pairs
 // A or B), written by the last pass but one when the index fits 32 - K bits.
+// Half: for 64-bit keys of one list, once the patterns of the low 32 bits are
+// done, (high 32 key bits, node) pairs of 8 bytes in the memory of pairs A or
+// B; the passes over the high half then run as 32-bit-key passes.
 enum BufKind : uint32_t {
-    kBufPairsA = 0, kBufPairsB = 1, kBufIdxA = 2, kBufIdxB = 3, kBufPackA = 4, kBufPackB = 5
+    kBufPairsA = 0, kBufPairsB = 1, kBufIdxA = 2, kBufIdxB = 3, kBufPackA = 4, kBufPackB = 5,
+    kBufHalfA = 6, kBufHalfB = 7
 };
+constexpr bool buf_in_b(uint32_t k)
+{
+    return k == kBufPairsB || k == kBufPackB || k == kBufHalfB;
+}
+constexpr bool buf_packed(uint32_t k) { return k == kBufPackA || k == kBufPackB; }
+constexpr bool buf_half(uint32_t k) { return k == kBufHalfA || k == kBufHalfB; }
+constexpr bool buf_pairs(uint32_t k) { return k == kBufPairsA || k == kBufPairsB; }
 
 struct PassSched {
     uint32_t skip;      // every element has the same digit: the pass is the identity
@@ -131,6 +142,9 @@ struct Plan {
     uint64_t n;
     uint32_t M, K, RB, radix, passes, flags, key_bytes;
     uint32_t tile, tiles;
+    uint32_t hi_from;     // one list of 64-bit keys: first pass over the high half (else passes)
+    uint32_t tiles_hi;    // tiles of those passes (32-bit-key shape)
+    uint32_t look_tiles;  // look-back words per pass and digit: max(tiles, tiles_hi)
     uint32_t spin_limit;  // look-back sleeps on one predecessor before the fallback
     uint32_t look64;      // 64-bit look-back words (counts of 2^30 and more)
     uint32_t num_lists;   // many-list sorts

@@ -84,13 +84,13 @@ __global__ __launch_bounds__(256) void k_walk0(const NodeRec<KeyT>* __restrict__
                                                uint32_t walk_blocks,
                                                const uint32_t* __restrict__ hist,
                                                uint32_t* __restrict__ dbase, uint32_t passes,
-                                               uint32_t radix)
+                                               uint32_t radix, uint32_t hi_from)
 {
     constexpr uint32_t C = SegLen<KeyT>::value;
     if (blockIdx.x == walk_blocks) {
         // one extra block: the pass schedule needs only pack's histograms, so
         // it runs beside the walk instead of as a launch of its own
-        schedule_body(hist, dbase, passes, n, radix, hdr);
+        schedule_body(hist, dbase, passes, n, radix, hdr, hi_from);
         return;
     }
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -498,7 +498,7 @@ static hipError_t launch_walk0(const Plan& P, uint32_t head, char* ws, hipStream
                        (Entry<KeyT>*)(ws + L.o_ent), (uint32_t*)(ws + L.o_resume), L.cap,
                        (uint32_t*)(ws + L.o_long), (Header*)(ws + P.o_header), walk_blocks,
                        (const uint32_t*)(ws + P.o_hist), (uint32_t*)(ws + P.o_dbase), P.passes,
-                       P.radix);
+                       P.radix, P.hi_from);
     return hipGetLastError();
 }
 

@@ -77,35 +77,55 @@ static hipError_t launch_pack(const Plan& P, const uint32_t* next, const void* k
 // The digit passes, least-significant pattern first.  One list: the
 // schedule has run (as one extra block of the level-0 walk) unless
 // `scheduled` is false.  SEG: many lists in segments, each pass with its
-// per-segment base table (the schedule ran with the base scan).
+// per-segment base table (the schedule ran with the base scan).  One list of
+// 64-bit keys: the passes from P.hi_from on (the high 32 key bits) run as
+// 32-bit-key passes with the 32-bit tile shape.
 template <typename KeyT, int RB, typename LW, bool SEG>
 static hipError_t launch_passes_rb(const Plan& P, char* ws, hipStream_t s, Prof* prof,
                                    bool scheduled)
 {
     constexpr int BLOCK = PassShape<KeyT, RB>::block;
     constexpr int ITEMS = PassShape<KeyT, RB>::items;
+    constexpr int BLOCK_HI = PassShape<uint32_t, RB>::block;
+    constexpr int ITEMS_HI = PassShape<uint32_t, RB>::items;
     constexpr uint32_t RADIX = 1u << RB;
     hipError_t e;
     if (!SEG && !scheduled) {
         mark(prof, s, kStageSchedule);
         hipLaunchKernelGGL((k_schedule<RB>), dim3(1), dim3(256), 0, s,
                            (const uint32_t*)(ws + P.o_hist), (uint32_t*)(ws + P.o_dbase),
-                           P.passes, (uint32_t)P.n, (Header*)(ws + P.o_header));
+                           P.passes, (uint32_t)P.n, (Header*)(ws + P.o_header), P.hi_from);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }
     const uint32_t ticket = (P.flags & PBIT_SHARED) ? 1u : 0u;
     const uint32_t group = 8u * kPassChunk;
-    const uint32_t grid = ticket ? P.tiles : (uint32_t)((P.tiles + group - 1) / group * group);
+    auto grid_of = [&](uint32_t tiles) {
+        return ticket ? tiles : (uint32_t)((tiles + group - 1) / group * group);
+    };
     for (uint32_t p = 0; p < P.passes; p++) {
-        LW* look = (LW*)(ws + P.o_look) + (size_t)p * P.tiles * RADIX;
+        LW* look = (LW*)(ws + P.o_look) + (size_t)p * P.look_tiles * RADIX;
         const uint32_t* dbase = SEG ? nullptr : (const uint32_t*)(ws + P.o_dbase) + (size_t)p * RADIX;
         SegMap sm{};
         if (SEG)
             sm = SegMap{(const uint32_t*)(ws + P.o_ctable), (const uint32_t*)(ws + P.o_coff),
                         (const uint32_t*)(ws + P.o_lbase) + (size_t)p * P.seg_max * RADIX};
         mark(prof, s, kStagePass);
-        hipLaunchKernelGGL((k_digit_pass<KeyT, RB, BLOCK, ITEMS, LW, SEG>), dim3(grid),
+        if constexpr (!SEG && sizeof(KeyT) == 8) {
+            if (p >= P.hi_from) {
+                hipLaunchKernelGGL(
+                    (k_digit_pass<uint32_t, RB, BLOCK_HI, ITEMS_HI, LW, false, true>),
+                    dim3(grid_of(P.tiles_hi)), dim3(BLOCK_HI), 0, s, p, p * RB - 32u,
+                    (uint32_t)P.n, (Pair<uint32_t>*)(ws + P.o_pairsA),
+                    (Pair<uint32_t>*)(ws + P.o_pairsB), (uint32_t*)(ws + P.o_idxA),
+                    (uint32_t*)(ws + P.o_idxB), dbase, look, (Header*)(ws + P.o_header), sm,
+                    P.spin_limit, ticket);
+                if ((e = hipGetLastError()) != hipSuccess)
+                    return e;
+                continue;
+            }
+        }
+        hipLaunchKernelGGL((k_digit_pass<KeyT, RB, BLOCK, ITEMS, LW, SEG>), dim3(grid_of(P.tiles)),
                            dim3(BLOCK), 0, s, p, p * RB, (uint32_t)P.n,
                            (Pair<KeyT>*)(ws + P.o_pairsA), (Pair<KeyT>*)(ws + P.o_pairsB),
                            (uint32_t*)(ws + P.o_idxA), (uint32_t*)(ws + P.o_idxB), dbase, look,

@@ -52,9 +52,17 @@ def test_packed_digit_passes():
     # one node more and the indices no longer fit below an 8-bit digit
     assert not bytemodel.packs_last_pass((1 << 24) + 1, 8, 4)
     assert bytemodel.digit_pass_bytes_per_node(4, 4, (1 << 24) + 1, 8) == (16 * 3 + 12) / 4
-    # 4-bit digits pack up to 2^28 nodes; u64 pairs are 12 bytes
+    # 4-bit digits pack up to 2^28 nodes
     assert bytemodel.packs_last_pass(1 << 28, 4, 16)
-    assert bytemodel.digit_pass_bytes_per_node(8, 8, 1 << 20, 8) == (24 * 6 + 16 + 8) / 8
     # a single executed pass reads pairs and writes indices
     assert bytemodel.digit_pass_bytes_per_node(4, 1, 1000, 8) == 12
     assert bytemodel.digit_pass_bytes_per_node(4, 0, 1000, 8) == 0
+
+
+def test_u64_passes_over_the_high_half():
+    # u64, K = 8, 2^26 nodes: passes 0-2 move 12-byte pairs, pass 3 writes
+    # 8-byte (high half, index) pairs, passes 4-6 move those, pass 7 reads
+    # them and writes indices
+    assert bytemodel.digit_pass_bytes_per_node(8, 8, 1 << 26, 8) == (24 * 3 + 20 + 16 * 3 + 12) / 8
+    # at 2^24 nodes the last two passes exchange packed words as well
+    assert bytemodel.digit_pass_bytes_per_node(8, 8, 1 << 24, 8) == (24 * 3 + 20 + 16 * 2 + 12 + 8) / 8
