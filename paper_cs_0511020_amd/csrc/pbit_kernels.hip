@@ -364,7 +364,21 @@ __global__ __launch_bounds__(kRelinkThreads) void k_relink_bucket(
     __shared__ uint32_t s_wsum[kRelinkThreads / 64];
     __shared__ __attribute__((aligned(16))) uint2 s_pairs[kRelinkTile];
     const int32_t st = hdr->status;
+    const uint32_t kind = hdr->final_kind;
     const uint32_t tid = threadIdx.x, t = blockIdx.x;
+    const uint64_t base = (uint64_t)t * kRelinkTile;
+    const uint32_t cnt = (uint32_t)min<uint64_t>(kRelinkTile, (uint64_t)n - base);
+    // the tile's order is loaded together with the status, from the index
+    // buffer the last pass writes; it is loaded again from where it is when
+    // no pass ran
+    uint32_t node[kRelinkItems], succ[kRelinkItems], slot[kRelinkItems];
+#pragma unroll
+    for (int i = 0; i < kRelinkItems; i++) {
+        const uint32_t k = (uint32_t)i * kRelinkThreads + tid;
+        const uint64_t j = base + k;
+        node[i] = k < cnt ? src.idxA[j] : kNil;
+        succ[i] = k < cnt && j + 1 < n ? src.idxA[j + 1] : kNil;
+    }
     if (st != 0) {
         if (t == 0 && tid == 0) {
             result[0] = kNil;
@@ -372,30 +386,27 @@ __global__ __launch_bounds__(kRelinkThreads) void k_relink_bucket(
         }
         return;
     }
-    const uint32_t kind = hdr->final_kind;
+    if (kind != kBufIdxA) {
+#pragma unroll
+        for (int i = 0; i < kRelinkItems; i++) {
+            const uint32_t k = (uint32_t)i * kRelinkThreads + tid;
+            const uint64_t j = base + k;
+            node[i] = k < cnt ? order_at(src, kind, j) : kNil;
+            succ[i] = k < cnt && j + 1 < n ? order_at(src, kind, j + 1) : kNil;
+        }
+    }
     // the pairs go to a buffer the order is not read from
     uint2* pairs = kind == kBufPairsA ? pairsB : pairsA;
-    const uint64_t base = (uint64_t)t * kRelinkTile;
-    const uint32_t cnt = (uint32_t)min<uint64_t>(kRelinkTile, (uint64_t)n - base);
     for (uint32_t i = tid; i <= kRelinkRangesMax; i += kRelinkThreads)
         s_cnt[i] = 0;
     __syncthreads();
-    uint32_t node[kRelinkItems], succ[kRelinkItems], slot[kRelinkItems];
 #pragma unroll
     for (int i = 0; i < kRelinkItems; i++) {
-        const uint32_t k = (uint32_t)i * kRelinkThreads + tid;
-        node[i] = kNil;
-        succ[i] = kNil;
         slot[i] = 0;
-        if (k < cnt) {
-            const uint64_t j = base + k;
-            const uint32_t v = order_at(src, kind, j);
-            succ[i] = j + 1 < n ? order_at(src, kind, j + 1) : kNil;
-            if (v < n) {
-                node[i] = v;
-                slot[i] = atomicAdd(&s_cnt[v >> r], 1u);  // any order inside a range
-            }
-        }
+        if (node[i] < n)
+            slot[i] = atomicAdd(&s_cnt[node[i] >> r], 1u);  // any order inside a range
+        else
+            node[i] = kNil;
     }
     __syncthreads();
     // exclusive scan of the range counts (one entry per thread)
@@ -447,17 +458,20 @@ __global__ __launch_bounds__(kRelinkThreads) void k_relink_ranges(
     char* __restrict__ out_base, uint64_t out_stride, const Header* hdr)
 {
     __shared__ uint32_t s_next[R];
+    const uint32_t b = blockIdx.x, tid = threadIdx.x;
+    const uint32_t* s0 = rstart + (size_t)b * ntiles;
+    const uint32_t* s1 = rstart + (size_t)(b + 1) * ntiles;
+    // the first tile's segment bounds are loaded together with the status
+    const uint32_t a0 = tid < ntiles ? s0[tid] : 0u;
+    const uint32_t e0 = tid < ntiles ? s1[tid] : 0u;
     if (hdr->status != 0)
         return;
     const uint2* pairs = hdr->final_kind == kBufPairsA ? pairsB : pairsA;
-    const uint32_t b = blockIdx.x, tid = threadIdx.x;
     const uint64_t lo = (uint64_t)b * R;
     const uint32_t len = (uint32_t)min<uint64_t>(R, (uint64_t)n - lo);
-    const uint32_t* s0 = rstart + (size_t)b * ntiles;
-    const uint32_t* s1 = rstart + (size_t)(b + 1) * ntiles;
     for (uint32_t t = tid; t < ntiles; t += kRelinkThreads) {
-        const uint32_t a = t < ntiles ? s0[t] : 0u;
-        const uint32_t e = t < ntiles ? min(s1[t], kRelinkTile) : 0u;
+        const uint32_t a = t == tid ? a0 : s0[t];
+        const uint32_t e = min(t == tid ? e0 : s1[t], kRelinkTile);
         const uint2* p = pairs + (uint64_t)t * kRelinkTile;
         for (uint32_t k0 = a; k0 < e; k0 += kRelinkBlock) {
             uint2 q[kRelinkBlock];
