@@ -536,9 +536,14 @@ __global__ __launch_bounds__(256) void k_unchain(const uint2* __restrict__ chain
 // of 64-bit keys, passes from `hi_from` on (the high 32 key bits) run as
 // 32-bit-key passes over (high half, node) pairs, which the last running
 // pass before them writes.
-__device__ __forceinline__ void assign_kinds(const uint32_t* skip, uint32_t passes, Header* hdr,
-                                             bool packable = false, uint32_t rb = 0,
-                                             uint32_t hi_from = kMaxPasses)
+// The buffer of each pass (in, out, and the packed digit's position) from
+// the passes that run, handed to emit(p, in, out, pk_shift); returns the
+// buffer holding the sorted order.  Also used on the host, with no pass
+// skipped, for the buffer a pass can expect before it reads the schedule.
+template <class Emit>
+__host__ __device__ inline uint32_t pass_kinds(const uint32_t* skip, uint32_t passes,
+                                               bool packable, uint32_t rb, uint32_t hi_from,
+                                               Emit emit)
 {
     int last = -1, prev = -1;
     for (uint32_t p = 0; p < passes; p++)
@@ -549,33 +554,46 @@ __device__ __forceinline__ void assign_kinds(const uint32_t* skip, uint32_t pass
     const bool packed = packable && prev >= 0;
     uint32_t cur = kBufPairsA;
     for (uint32_t p = 0; p < passes; p++) {
-        PassSched ps = hdr->sched[p];
-        ps.skip = skip[p];
-        ps.in_kind = cur;
-        ps.pk_shift = 0;
+        uint32_t pk_shift = 0;
         // the next pass that runs after p
         int next = -1;
         for (uint32_t q = p + 1; q < passes && next < 0; q++)
             if (!skip[q])
                 next = (int)q;
         const bool b = !buf_in_b(cur);  // the other buffer
+        uint32_t out;
         if ((int)p == last) {
-            ps.out_kind = kBufIdxA;
+            out = kBufIdxA;
         } else if (packed && (int)p == prev) {
-            ps.out_kind = b ? kBufPackB : kBufPackA;
+            out = b ? kBufPackB : kBufPackA;
             // the digit's bit position in the writer's own key (a high-half
             // pass holds key bits 32.. only)
-            ps.pk_shift = (uint32_t)last * rb - (p >= hi_from ? 32u : 0u);
+            pk_shift = (uint32_t)last * rb - (p >= hi_from ? 32u : 0u);
         } else if (next >= (int)hi_from) {
-            ps.out_kind = b ? kBufHalfB : kBufHalfA;
+            out = b ? kBufHalfB : kBufHalfA;
         } else {
-            ps.out_kind = b ? kBufPairsB : kBufPairsA;
+            out = b ? kBufPairsB : kBufPairsA;
         }
-        if (!ps.skip)
-            cur = ps.out_kind;
-        hdr->sched[p] = ps;
+        emit(p, cur, out, pk_shift);
+        if (!skip[p])
+            cur = out;
     }
-    hdr->final_kind = cur;
+    return cur;
+}
+
+__device__ __forceinline__ void assign_kinds(const uint32_t* skip, uint32_t passes, Header* hdr,
+                                             bool packable = false, uint32_t rb = 0,
+                                             uint32_t hi_from = kMaxPasses)
+{
+    hdr->final_kind = pass_kinds(skip, passes, packable, rb, hi_from,
+                                 [&](uint32_t p, uint32_t in, uint32_t out, uint32_t pk) {
+                                     PassSched ps = hdr->sched[p];
+                                     ps.skip = skip[p];
+                                     ps.in_kind = in;
+                                     ps.out_kind = out;
+                                     ps.pk_shift = pk;
+                                     hdr->sched[p] = ps;
+                                 });
 }
 
 // Per pass (one list): exclusive scan of the digit counts (global digit
@@ -708,7 +726,7 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
     uint32_t pass, uint32_t shift, uint32_t n_all, Pair<KeyT>* __restrict__ pairsA,
     Pair<KeyT>* __restrict__ pairsB, uint32_t* __restrict__ idxA, uint32_t* __restrict__ idxB,
     const uint32_t* __restrict__ dbase, LW* __restrict__ look, Header* hdr, SegMap sm,
-    uint32_t spin_limit, uint32_t ticket)
+    uint32_t spin_limit, uint32_t ticket, uint32_t exp_in)
 {
     using LK = Look<LW>;
     constexpr uint32_t RADIX = 1u << RB;
@@ -726,6 +744,44 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
     // per wave (it is staged into only afterwards)
     static_assert((size_t)WAVES * RADIX * 8 <= sizeof(KV<KeyT>) * TILE, "peer masks fit in s_kv");
     unsigned long long* s_mask = (unsigned long long*)s_kv;
+
+    KeyT key[ITEMS];
+    uint32_t idx[ITEMS], dig[ITEMS], rank[ITEMS];
+    // With the default tile order the tile is known from the block index, so
+    // (one list) its elements are loaded before the status and the schedule
+    // are read, from the buffer `exp_in` the host expects when no pattern is
+    // skipped (pairs of this kernel's width, or packed words); a pass whose
+    // input is elsewhere loads again below.  The addresses are valid whatever
+    // the buffers hold.
+    bool early = false;
+    if constexpr (!SEG && sizeof(Pair<KeyT>) == 8) {
+        const bool packed_exp = buf_packed(exp_in);
+        const bool pairs_exp = HI ? buf_half(exp_in) : buf_pairs(exp_in);
+        if (!ticket && (packed_exp || pairs_exp)) {
+            const uint32_t q0 = blockIdx.x / 8u;
+            const uint64_t t0 = (uint64_t)((q0 / kPassChunk) * (8u * kPassChunk) +
+                                           (blockIdx.x % 8u) * kPassChunk + q0 % kPassChunk);
+            const uint64_t wb = t0 * TILE + (uint64_t)(threadIdx.x / 64) * (64 * ITEMS);
+            const uint32_t ln = threadIdx.x % 64;
+            const Pair<KeyT>* src = buf_in_b(exp_in) ? pairsB : pairsA;
+            early = true;
+#pragma unroll
+            for (int i = 0; i < ITEMS; i++) {
+                const uint64_t e = wb + (uint64_t)i * 64 + ln;
+                key[i] = 0;
+                idx[i] = 0;
+                if (e < n_all) {
+                    if (packed_exp) {
+                        idx[i] = ((const uint32_t*)src)[e];
+                    } else {
+                        const Pair<KeyT> v = src[e];
+                        key[i] = pair_key<KeyT>(v);
+                        idx[i] = v.idx;
+                    }
+                }
+            }
+        }
+    }
 
     if (hdr->status != 0)
         return;
@@ -788,9 +844,27 @@ __global__ __launch_bounds__(BLOCK, (PassShape<KeyT, RB>::waves)) void k_digit_p
         __syncthreads();
     }
 
-    KeyT key[ITEMS];
-    uint32_t idx[ITEMS], dig[ITEMS], rank[ITEMS];
-    if (!SEG && in_packed) {
+    if (early && ps.in_kind == exp_in) {
+        // the elements loaded early: digits (packed words: digit and node)
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++) {
+            const uint64_t e = wbase + (uint64_t)i * 64 + lane;
+            if (e < n) {
+                if (in_packed) {
+                    const uint32_t v = idx[i];
+                    dig[i] = v >> PK;
+                    idx[i] = v & ((1u << PK) - 1u);
+                    key[i] = (KeyT)((KeyT)dig[i] << shift);
+                } else {
+                    dig[i] = (uint32_t)(key[i] >> shift) & (RADIX - 1u);
+                }
+            } else {
+                key[i] = 0;
+                idx[i] = 0;
+                dig[i] = RADIX;
+            }
+        }
+    } else if (!SEG && in_packed) {
         // the key is only needed for this pass's digit: it is kept in place
 #pragma unroll
         for (int i = 0; i < ITEMS; i++) {

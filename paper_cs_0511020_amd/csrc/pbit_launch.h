@@ -103,6 +103,16 @@ static hipError_t launch_passes_rb(const Plan& P, char* ws, hipStream_t s, Prof*
     auto grid_of = [&](uint32_t tiles) {
         return ticket ? tiles : (uint32_t)((tiles + group - 1) / group * group);
     };
+    // the buffer each pass reads when no pattern is skipped (one list): the
+    // pass loads its tile from there before it reads the schedule
+    uint32_t exp_in[kMaxPasses];
+    for (uint32_t p = 0; p < P.passes; p++)
+        exp_in[p] = kNil;
+    if (!SEG) {
+        const uint32_t none[kMaxPasses] = {};
+        pass_kinds(none, P.passes, P.n <= (1ull << (32 - RB)), RB, P.hi_from,
+                   [&](uint32_t p, uint32_t in, uint32_t, uint32_t) { exp_in[p] = in; });
+    }
     for (uint32_t p = 0; p < P.passes; p++) {
         LW* look = (LW*)(ws + P.o_look) + (size_t)p * P.look_tiles * RADIX;
         const uint32_t* dbase = SEG ? nullptr : (const uint32_t*)(ws + P.o_dbase) + (size_t)p * RADIX;
@@ -119,7 +129,7 @@ static hipError_t launch_passes_rb(const Plan& P, char* ws, hipStream_t s, Prof*
                     (uint32_t)P.n, (Pair<uint32_t>*)(ws + P.o_pairsA),
                     (Pair<uint32_t>*)(ws + P.o_pairsB), (uint32_t*)(ws + P.o_idxA),
                     (uint32_t*)(ws + P.o_idxB), dbase, look, (Header*)(ws + P.o_header), sm,
-                    P.spin_limit, ticket);
+                    P.spin_limit, ticket, exp_in[p]);
                 if ((e = hipGetLastError()) != hipSuccess)
                     return e;
                 continue;
@@ -129,7 +139,7 @@ static hipError_t launch_passes_rb(const Plan& P, char* ws, hipStream_t s, Prof*
                            dim3(BLOCK), 0, s, p, p * RB, (uint32_t)P.n,
                            (Pair<KeyT>*)(ws + P.o_pairsA), (Pair<KeyT>*)(ws + P.o_pairsB),
                            (uint32_t*)(ws + P.o_idxA), (uint32_t*)(ws + P.o_idxB), dbase, look,
-                           (Header*)(ws + P.o_header), sm, P.spin_limit, ticket);
+                           (Header*)(ws + P.o_header), sm, P.spin_limit, ticket, exp_in[p]);
         e = hipGetLastError();
         if (e != hipSuccess)
             return e;
